@@ -1,0 +1,252 @@
+"""CPU oracle of the per-frame fusion path (binary64, plain loops).
+
+TEST INFRASTRUCTURE ONLY: imported by `tests/`, `__graft_entry__.smoke()` and the
+CPU-baseline leg of `bench.py`, never by the product package.  The C source,
+`itm_oracle.c`, shares nothing with the GPU library; see its header for which
+section of the paper each function follows.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "itm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# binary64 everywhere, no contraction of a*b+c, no fast-math: decisions taken in
+# binary32 must round exactly as written
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC",
+          "-shared"]
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+_P = C.c_void_p
+_i64, _i32, _u32, _f32 = C.c_int64, C.c_int32, C.c_uint32, C.c_float
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        L = C.CDLL(_LIB)
+        sig = {
+            "orc_hash_index": (_u32, [_i32, _i32, _i32, _u32]),
+            "orc_scene_create": (_P, [_f32, _f32, _i32, _i64, _i64]),
+            "orc_scene_destroy": (None, [_P]),
+            "orc_set_range": (C.c_int, [_P, _f32, _f32]),
+            "orc_find": (_i64, [_P, _i32, _i32, _i32]),
+            "orc_insert": (_i64, [_P, _i32, _i32, _i32]),
+            "orc_dda_blocks": (_i64, [_P, _P, _P, _i64]),
+            "orc_segment": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, C.c_int, C.c_int, _f32, _P, _P]),
+            "orc_allocate": (_i64, [_P, _P, C.c_int, C.c_int, _P, _P]),
+            "orc_integrate": (_i64, [_P, _P, C.c_int, C.c_int, _P, _P]),
+            "orc_visible_keys": (_i64, [_P, _P, _i64]),
+            "orc_stats": (None, [_P, _P]),
+            "orc_entries": (None, [_P, _P, _P, _P]),
+            "orc_export": (_i64, [_P, _P, _P, _P, _i64]),
+            "orc_update_voxels": (_i64, [_P, _P, C.c_int, C.c_int, _P, _P, _P, _P, _i64, _P, _P]),
+            "orc_dense_create": (_P, [_i64, _i64, _i64, _i64, _i64, _i64, _f32, _f32, _i32]),
+            "orc_dense_destroy": (None, [_P]),
+            "orc_dense_integrate": (_i64, [_P, _P, C.c_int, C.c_int, _P, _P, _P, _i64]),
+            "orc_dense_read": (None, [_P, _P, _P, _P]),
+            "orc_raycast": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P]),
+            "orc_raycast_crossing": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
+            "orc_num_threads": (C.c_int, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def hash_index(x: int, y: int, z: int, mask: int) -> int:
+    return int(lib().orc_hash_index(x, y, z, mask))
+
+
+def dda_blocks(P0, P1) -> np.ndarray:
+    """Blocks crossed by the segment P0 -> P1 (binary32 block units), in visit order."""
+    a = np.ascontiguousarray(P0, np.float32)
+    b = np.ascontiguousarray(P1, np.float32)
+    n = lib().orc_dda_blocks(_ptr(a), _ptr(b), None, 0)
+    out = np.empty((n, 3), np.int32)
+    lib().orc_dda_blocks(_ptr(a), _ptr(b), _ptr(out), n)
+    return out
+
+
+def _K(intr):
+    return np.ascontiguousarray(intr, np.float64)
+
+
+class Scene:
+    """Hashed TSDF volume on the CPU (the paper's voxel block hashing)."""
+
+    def __init__(self, voxel_size, mu, max_w, n_buckets, n_excess):
+        self.h = lib().orc_scene_create(voxel_size, mu, max_w, n_buckets, n_excess)
+        if not self.h:
+            raise ValueError("invalid oracle scene parameters")
+        self.voxel_size, self.mu, self.max_w = voxel_size, mu, max_w
+        self.n_buckets, self.n_excess = n_buckets, n_excess
+        self.n_entries = 2 * n_buckets + n_excess
+
+    @classmethod
+    def from_params(cls, p):
+        return cls(p["voxel_size"], p["mu"], p["max_w"], p["n_buckets"], p["n_excess"])
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_scene_destroy(self.h)
+            self.h = None
+
+    def set_range(self, z_near, z_far):
+        if lib().orc_set_range(self.h, z_near, z_far) != 0:
+            raise ValueError("bad range")
+
+    def find(self, x, y, z) -> int:
+        return int(lib().orc_find(self.h, x, y, z))
+
+    def insert(self, x, y, z) -> int:
+        return int(lib().orc_insert(self.h, x, y, z))
+
+    def segment(self, depth_value, u, v, W, H, intr, T_wc):
+        P0 = np.zeros(3, np.float32)
+        P1 = np.zeros(3, np.float32)
+        ok = lib().orc_segment(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                               u, v, depth_value, _ptr(P0), _ptr(P1))
+        return (P0, P1) if ok else None
+
+    def allocate(self, depth, intr, T_wc) -> int:
+        d = np.ascontiguousarray(depth, np.float32)
+        H, W = d.shape
+        return int(lib().orc_allocate(self.h, _ptr(d), W, H, _ptr(_K(intr)),
+                                      _ptr(np.ascontiguousarray(T_wc, np.float64))))
+
+    def integrate(self, depth, intr, T_wc) -> int:
+        """Allocation then integration of one frame; returns updated voxel count."""
+        d = np.ascontiguousarray(depth, np.float32)
+        H, W = d.shape
+        r = int(lib().orc_integrate(self.h, _ptr(d), W, H, _ptr(_K(intr)),
+                                    _ptr(np.ascontiguousarray(T_wc, np.float64))))
+        if r < 0:
+            raise MemoryError("oracle integrate failed")
+        return r
+
+    def visible_keys(self) -> np.ndarray:
+        n = lib().orc_visible_keys(self.h, None, 0)
+        out = np.empty((n, 3), np.int32)
+        lib().orc_visible_keys(self.h, _ptr(out), n)
+        return out
+
+    def stats(self) -> dict:
+        out = np.zeros(8, np.int64)
+        lib().orc_stats(self.h, _ptr(out))
+        keys = ["n_allocated", "n_visible", "n_excess_used", "n_dropped_total", "excess_demand",
+                "n_updated_last"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def entries(self):
+        n = self.n_entries
+        pos = np.empty((n, 3), np.int16)
+        off = np.empty(n, np.int32)
+        ptr = np.empty(n, np.int32)
+        lib().orc_entries(self.h, _ptr(pos), _ptr(off), _ptr(ptr))
+        return pos, off, ptr
+
+    def export(self, with_values=True):
+        n = lib().orc_export(self.h, None, None, None, 0)
+        coords = np.empty((n, 3), np.int32)
+        F = np.empty((n, 512), np.float64) if with_values else None
+        Wt = np.empty((n, 512), np.int32) if with_values else None
+        lib().orc_export(self.h, _ptr(coords), _ptr(F), _ptr(Wt), n)
+        return coords, F, Wt
+
+    def update_voxels(self, depth, intr, T_wc, vox, active, F, Wt) -> int:
+        """Apply one frame's update to individual voxels (absolute voxel coords)."""
+        d = np.ascontiguousarray(depth, np.float32)
+        H, W = d.shape
+        vox = np.ascontiguousarray(vox, np.int32)
+        act = np.ascontiguousarray(active, np.uint8)
+        assert F.dtype == np.float64 and Wt.dtype == np.int32 and F.flags.c_contiguous
+        return int(lib().orc_update_voxels(self.h, _ptr(d), W, H, _ptr(_K(intr)),
+                                           _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                                           _ptr(vox), _ptr(act), len(vox), _ptr(F), _ptr(Wt)))
+
+    def raycast(self, W, H, intr, T_wc):
+        """Returns (pts [H,W,4], normals [H,W,4], camera depth [H,W], flags, steps)."""
+        pts = np.empty((H, W, 4), np.float64)
+        nrm = np.empty((H, W, 4), np.float64)
+        zc = np.empty((H, W), np.float64)
+        fl = np.empty((H, W), np.uint8)
+        st = np.empty((H, W), np.int32)
+        lib().orc_raycast(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                          _ptr(pts), _ptr(nrm), _ptr(zc), _ptr(fl), _ptr(st))
+        return pts, nrm, zc, fl, st
+
+    def raycast_crossing(self, W, H, intr, T_wc):
+        zc = np.empty((H, W), np.float64)
+        lib().orc_raycast_crossing(self.h, W, H, _ptr(_K(intr)),
+                                   _ptr(np.ascontiguousarray(T_wc, np.float64)), _ptr(zc))
+        return zc
+
+
+class Dense:
+    """Dense TSDF grid on the CPU (the paper's plain voxel array)."""
+
+    def __init__(self, origin, size, voxel_size, mu, max_w):
+        self.size = tuple(int(s) for s in size)
+        self.origin = tuple(int(o) for o in origin)
+        self.h = lib().orc_dense_create(*self.origin, *self.size, voxel_size, mu, max_w)
+        if not self.h:
+            raise ValueError("invalid dense grid")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_dense_destroy(self.h)
+            self.h = None
+
+    def integrate(self, depth, intr, T_wc, mask_keys=None) -> int:
+        d = np.ascontiguousarray(depth, np.float32)
+        H, W = d.shape
+        mk = None if mask_keys is None else np.ascontiguousarray(mask_keys, np.int32)
+        return int(lib().orc_dense_integrate(self.h, _ptr(d), W, H, _ptr(_K(intr)),
+                                             _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                                             _ptr(mk), 0 if mk is None else len(mk)))
+
+    def read(self):
+        nx, ny, nz = self.size
+        F = np.empty((nz, ny, nx), np.float64)
+        Wt = np.empty((nz, ny, nx), np.int32)
+        fr = np.empty((nz, ny, nx), np.uint64)
+        lib().orc_dense_read(self.h, _ptr(F), _ptr(Wt), _ptr(fr))
+        return F, Wt, fr
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+def fuse_stream(stream, n_frames=None, scene=None):
+    """Run allocation + integration over the first n_frames of a synth.Stream."""
+    sc = scene or Scene.from_params(stream.params)
+    n = stream.n_frames if n_frames is None else n_frames
+    for f in range(n):
+        sc.integrate(stream.depth[f], stream.intrinsics, stream.T_wc[f])
+    return sc

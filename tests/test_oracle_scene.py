@@ -1,0 +1,255 @@
+"""Whole-frame pins of the oracle on small seeded streams.
+
+* allocation: the allocated block set equals the union, over frames and valid
+  pixels, of the blocks each band segment crosses (section "Allocation"), and the
+  hash table keeps its structure invariants (section "Hash Table Operations");
+* (a) the dense volume (section "Dense Volumes") and the hashed volume agree;
+* (b) a fused noise-free plane and sphere match their closed-form distances;
+* (c) the raycast of a plane (section "Raycast") matches its closed-form depth.
+"""
+import numpy as np
+import pytest
+
+from synth import Scene as SynthScene, make_stream, render_depth, pose_look_at
+
+
+def dda_union(orc, sc, stream, frames):
+    keys = set()
+    W, H = stream.width, stream.height
+    for f in range(frames):
+        d = stream.depth[f]
+        for v in range(H):
+            for u in range(W):
+                seg = sc.segment(d[v, u], u, v, W, H, stream.intrinsics, stream.T_wc[f])
+                if seg is None:
+                    continue
+                for b in orc.dda_blocks(*seg):
+                    keys.add(tuple(int(x) for x in b))
+    return keys
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return make_stream("tiny")
+
+
+@pytest.fixture(scope="module")
+def tiny_fused(orc, tiny):
+    sc = orc.Scene.from_params(tiny.params)
+    vis = []
+    for f in range(tiny.n_frames):
+        sc.integrate(tiny.depth[f], tiny.intrinsics, tiny.T_wc[f])
+        vis.append(sc.visible_keys())
+    return sc, vis
+
+
+def test_allocated_set_is_union_of_crossed_blocks(orc, tiny, tiny_fused):
+    sc, vis = tiny_fused
+    probe = orc.Scene.from_params(tiny.params)
+    want = dda_union(orc, probe, tiny, tiny.n_frames)
+    coords, _, _ = sc.export(with_values=False)
+    got = {tuple(int(x) for x in c) for c in coords}
+    assert sc.stats()["n_dropped_total"] == 0
+    assert got == want
+    # the last frame's visible set is exactly the blocks its own pixels cross
+    last = dda_union_frame(orc, probe, tiny, tiny.n_frames - 1)
+    assert {tuple(int(x) for x in k) for k in vis[-1]} == last
+
+
+def dda_union_frame(orc, sc, stream, f):
+    keys = set()
+    W, H = stream.width, stream.height
+    for v in range(H):
+        for u in range(W):
+            seg = sc.segment(stream.depth[f][v, u], u, v, W, H, stream.intrinsics, stream.T_wc[f])
+            if seg is not None:
+                keys.update(tuple(int(x) for x in b) for b in orc.dda_blocks(*seg))
+    return keys
+
+
+def test_hash_structure_invariants(orc, tiny, tiny_fused):
+    sc, _ = tiny_fused
+    pos, off, ptr = sc.entries()
+    nb = sc.n_buckets
+    used = ptr >= 0
+    keys = [tuple(p) for p in pos[used]]
+    assert len(set(keys)) == len(keys), "duplicate block keys"
+    p = ptr[used]
+    assert len(np.unique(p)) == len(p) and p.min() == 0 and p.max() == len(p) - 1
+    # every entry's key hashes to the bucket whose chain holds it
+    mask = nb - 1
+    for e in np.nonzero(used)[0]:
+        k = tuple(int(v) for v in pos[e])
+        assert sc.find(*k) == e
+        if e < 2 * nb:
+            assert e // 2 == orc.hash_index(*k, mask)
+    # chains are acyclic and only link excess entries
+    for b in range(nb):
+        o, seen = off[2 * b + 1] - 1, set()
+        while o >= 0:
+            assert o not in seen
+            seen.add(o)
+            assert ptr[2 * nb + o] >= 0
+            o = off[2 * nb + o] - 1
+    st = sc.stats()
+    assert st["n_excess_used"] == st["excess_demand"]
+
+
+def test_overflow_accounting(orc, tiny):
+    # a table far too small: 64 buckets and 8 excess entries
+    sc = orc.Scene(tiny.params["voxel_size"], tiny.params["mu"], 100, 64, 8)
+    sc.allocate(tiny.depth[0], tiny.intrinsics, tiny.T_wc[0])
+    want = dda_union_frame(orc, sc, tiny, 0)
+    per_bucket = {}
+    for k in want:
+        h = orc.hash_index(*k, 63)
+        per_bucket[h] = per_bucket.get(h, 0) + 1
+    D = sum(max(0, n - 2) for n in per_bucket.values())
+    st = sc.stats()
+    assert st["n_allocated"] == sum(min(n, 2) for n in per_bucket.values()) + min(D, 8)
+    assert st["n_dropped_total"] == max(0, D - 8)
+    coords, _, _ = sc.export(with_values=False)
+    assert {tuple(int(x) for x in c) for c in coords} <= want
+
+
+def test_dense_equals_hashed(orc, tiny, tiny_fused):
+    """(a) the same update run over a dense grid: masked to each frame's visible
+    blocks it reproduces the hashed volume exactly; unmasked it agrees wherever the
+    frames that updated a voxel all had its block visible."""
+    sc, vis = tiny_fused
+    coords, F, Wt = sc.export()
+    lo = coords.min(0) * 8
+    hi = coords.max(0) * 8 + 8
+    size = hi - lo
+    p = tiny.params
+    masked = orc.Dense(lo, size, p["voxel_size"], p["mu"], p["max_w"])
+    plain = orc.Dense(lo, size, p["voxel_size"], p["mu"], p["max_w"])
+    for f in range(tiny.n_frames):
+        masked.integrate(tiny.depth[f], tiny.intrinsics, tiny.T_wc[f], mask_keys=vis[f])
+        plain.integrate(tiny.depth[f], tiny.intrinsics, tiny.T_wc[f])
+    Fm, Wm, _ = masked.read()
+    Fp, Wp, frames = plain.read()
+    # hashed values scattered into the dense layout
+    l = np.arange(512)
+    lx, ly, lz = l % 8, (l // 8) % 8, l // 64
+    vx = (coords[:, 0:1] * 8 + lx - lo[0])
+    vy = (coords[:, 1:2] * 8 + ly - lo[1])
+    vz = (coords[:, 2:3] * 8 + lz - lo[2])
+    assert np.array_equal(Fm[vz, vy, vx], F)
+    assert np.array_equal(Wm[vz, vy, vx], Wt)
+    # outside allocated blocks the masked grid is untouched
+    assert Wm.sum() == Wt.sum()
+    # unmasked: compare voxels whose updating frames all had the block visible
+    vis_bits = np.zeros(len(coords), np.uint64)
+    index = {tuple(int(x) for x in c): i for i, c in enumerate(coords)}
+    for f, keys in enumerate(vis):
+        for k in keys:
+            vis_bits[index[tuple(int(x) for x in k)]] |= np.uint64(1 << f)
+    fr = frames[vz, vy, vx]
+    ok = (fr & ~vis_bits[:, None]) == 0
+    assert ok.mean() > 0.9
+    assert np.array_equal(Fp[vz, vy, vx][ok], F[ok])
+    assert np.array_equal(Wp[vz, vy, vx][ok], Wt[ok])
+
+
+def _plane_stream(Z0, n_frames=3, W=160, H=120, K=(140.0, 140.0, 80.0, 60.0)):
+    scene = SynthScene(planes=np.array([[0.0, 0.0, -1.0, -Z0]]))
+    T = np.eye(4)
+    d = render_depth(scene, K, W, H, T).astype(np.float32)
+    return np.stack([d] * n_frames), np.stack([T] * n_frames), K
+
+
+def test_plane_closed_form(orc):
+    """(b) noise-free fronto-parallel plane z = Z0 seen from the origin: every
+    updated voxel holds F = min(1, (Z0 - z_v) / mu) and W = number of frames."""
+    Z0, s, mu = 1.3, 0.01, 0.04
+    depth, T, K = _plane_stream(Z0)
+    assert np.all(depth == np.float32(Z0))
+    sc = orc.Scene(s, mu, 100, 2 ** 14, 2 ** 12)
+    for f in range(len(depth)):
+        sc.integrate(depth[f], K, T[f])
+    coords, F, Wt = sc.export()
+    l = np.arange(512)
+    z = (coords[:, 2:3] * 8 + l // 64) * float(np.float32(s))
+    want = np.minimum(1.0, (float(np.float32(Z0)) - z) / float(np.float32(mu)))
+    upd = Wt > 0
+    assert upd.sum() > 10000
+    assert np.all(Wt[upd] == len(depth))
+    assert np.abs(F[upd] - want[upd]).max() < 1e-12
+    # voxels behind the band by more than mu are never updated
+    eta = float(np.float32(Z0)) - z
+    assert not np.any(upd & (eta < -float(np.float32(mu)) - 1e-9))
+
+
+def test_sphere_zero_crossing(orc):
+    """(b) noise-free sphere on a plane (the tiny workload's geometry): the zero
+    crossing of the fused F between sign-changing neighbours along z lies within
+    1 mm of the analytic surface where the surface faces the camera."""
+    st = make_stream("tiny", noise=False)
+    sc = orc.fuse_stream(st)
+    coords, F, Wt = sc.export()
+    s = float(np.float32(st.params["voxel_size"]))
+    mu = float(np.float32(st.params["mu"]))
+    vol = {}
+    for c, f, w in zip(coords, F, Wt):
+        vol[tuple(int(x) for x in c)] = (f.reshape(8, 8, 8), w.reshape(8, 8, 8))
+    cen, r = st.scene.spheres[0][:3], st.scene.spheres[0][3]
+    errs = []
+    for (kx, ky, kz), (f, w) in vol.items():
+        for lz in range(7):
+            a, b = f[lz], f[lz + 1]
+            ok = (w[lz] > 0) & (w[lz + 1] > 0) & (a > 0) & (b <= 0)
+            for ly, lx in zip(*np.nonzero(ok)):
+                t = a[ly, lx] / (a[ly, lx] - b[ly, lx])
+                p = np.array([(kx * 8 + lx) * s, (ky * 8 + ly) * s, (kz * 8 + lz + t) * s])
+                q = p - cen
+                # the sphere's front cap (surface normal within 25 degrees of -z)
+                if np.linalg.norm(q) < 2 * r and -q[2] / np.linalg.norm(q) > np.cos(np.deg2rad(25)):
+                    errs.append(abs(np.linalg.norm(q) - r))
+    errs = np.array(errs)
+    assert len(errs) > 200
+    assert errs.max() < 1e-3
+
+
+def test_plane_raycast_closed_form(orc):
+    """(c) raycast of the fused fronto-parallel plane from the fusing pose: each
+    hit lies at camera depth Z0 up to the two-step refinement residual
+    2 s (1 - cos(theta))^2, theta the pixel ray's angle to the optical axis."""
+    Z0, s, mu = 1.3, 0.01, 0.04
+    depth, T, K = _plane_stream(Z0)
+    sc = orc.Scene(s, mu, 100, 2 ** 14, 2 ** 12)
+    for f in range(len(depth)):
+        sc.integrate(depth[f], K, T[f])
+    H, W = depth.shape[1:]
+    pts, nrm, zc, fl, st = sc.raycast(W, H, K, T[0])
+    hit = pts[..., 3] > 0
+    inner = np.zeros_like(hit)
+    inner[4:-4, 4:-4] = True   # voxels near the image border are never updated
+    assert hit[inner].all()
+    u, v = np.meshgrid(np.arange(W), np.arange(H))
+    cos_t = 1.0 / np.sqrt(((u - K[2]) / K[0]) ** 2 + ((v - K[3]) / K[1]) ** 2 + 1.0)
+    bound = 2 * s * (1 - cos_t) ** 2 + 1e-9
+    err = np.abs(zc - float(np.float32(Z0)))
+    assert np.all(err[inner] <= bound[inner])
+    # on-axis pixel is exact
+    assert err[60, 80] < 1e-9
+    # normals face the camera (-z)
+    assert np.all(nrm[inner][:, 2] < -0.99)
+
+
+def test_raycast_agrees_with_zero_crossing(orc, tiny):
+    """The state machine's hit and the first zero crossing of the interpolated F
+    along the ray agree on nearly every pixel of the fused tiny scene."""
+    sc = orc.fuse_stream(tiny)
+    W, H = tiny.width, tiny.height
+    pts, nrm, zc, fl, st = sc.raycast(W, H, tiny.intrinsics, tiny.T_wc[-1])
+    zx = sc.raycast_crossing(W, H, tiny.intrinsics, tiny.T_wc[-1])
+    both = (zc > 0) & (zx > 0)
+    assert both.mean() > 0.95
+    assert ((zc > 0) != (zx > 0)).mean() < 0.01
+    # the march steps by the projective distance of the fusing views, so at
+    # silhouettes and grazing angles it can land on a different crossing than the
+    # dense search; measured: 97.3% of co-hits within 1 mm, median 2e-5 m
+    d = np.abs(zc - zx)[both]
+    assert (d < 1e-3).mean() > 0.95
+    assert np.median(d) < 1e-4
