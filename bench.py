@@ -1,0 +1,202 @@
+#!/usr/bin/env python3
+"""Throughput of the per-frame fusion hot path on one MI355X.
+
+A step is one frame through the whole path: allocation, visible-list compaction,
+integration (itm_integrate) and a raycast from the frame's pose (itm_raycast), on a
+seeded synthetic VGA depth stream already resident in HBM.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps 290] [--warmup 10] [--fmt f32|f16|s16u8]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "integrated voxels/s + raycast rays/s at VGA, 5 mm; % HBM roofline"
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+SDF_BYTES = {"f32": 4, "f16": 2, "s16u8": 2}
+VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name, fmt, W, H, launches, vis_total, upd_total, n_entries):
+    """Algorithmic bytes per launch (the bytes the method itself must move)."""
+    if launches == 0:
+        return 0.0
+    vis = vis_total / launches
+    if name == "integrate":
+        # read + write F and W of every updated voxel
+        return 2.0 * VOX_BYTES[fmt] * upd_total / launches
+    if name == "alloc":
+        # the depth image + one 32-byte bucket record per visible block + flags
+        return 4.0 * W * H + 32.0 * vis + vis
+    if name == "compact":
+        # read every flag, clear the set ones, write the list
+        return float(n_entries) + vis + 4.0 * vis
+    if name == "raycast":
+        # two float4 maps out + the F values of the blocks in view (estimated by
+        # the frame's visible blocks) + one bucket record each
+        return 32.0 * W * H + vis * (512.0 * SDF_BYTES[fmt] + 32.0)
+    return 0.0
+
+
+def cpu_baseline(stream, seconds):
+    """The CPU oracle (allocation + integration, plain loops) on the first frames
+    of the same stream until about `seconds` of work."""
+    import oracle
+    sc = oracle.Scene.from_params(stream.params)
+    vox, t0, n = 0, time.perf_counter(), 0
+    while n < stream.n_frames:
+        sc.integrate(stream.depth[n], stream.intrinsics, stream.T_wc[n])
+        vox += sc.stats()["n_visible"] * 512
+        n += 1
+        if time.perf_counter() - t0 > seconds:
+            break
+    t_int = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    sc.raycast(stream.width, stream.height, stream.intrinsics, stream.T_wc[n - 1])
+    t_rc = time.perf_counter() - t1
+    return {"value": vox / t_int, "unit": "voxels/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"frames 0..{n - 1} of the same stream, allocation + integration "
+                      f"({t_int:.1f} s); raycast of frame {n - 1}: "
+                      f"{stream.width * stream.height / t_rc:.3g} rays/s",
+            "rays_per_s": stream.width * stream.height / t_rc}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=290)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--fmt", default="f32", choices=sorted(SDF_BYTES))
+    ap.add_argument("--workload", default="vga", choices=["vga", "large", "tiny"])
+    ap.add_argument("--no-events", action="store_true", help="skip per-kernel HIP events")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="after the timed region, copy a buffer of this size once "
+                         "(reference kernel for hardware byte counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU: the fusion path is measured on a single MI355X "
+              "(multi-GPU sharding is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1410_0925_amd as itm
+    from synth import make_stream, workload_params
+
+    if not os.path.exists(itm.LIB_PATH):
+        from paper_1410_0925_amd import build
+        build.build()
+    torch.cuda.set_device(0)
+
+    p = workload_params(args.workload)
+    n_frames = max(p["n_frames"], args.steps + args.warmup)
+    t0 = time.perf_counter()
+    st = make_stream(args.workload, n_frames=n_frames)
+    log(f"stream {args.workload}: {n_frames} frames {st.width}x{st.height} generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+    W, H = st.width, st.height
+    K = tuple(st.intrinsics) + (W, H)
+    depth = torch.from_numpy(st.depth).cuda()
+    pts = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+
+    sc = itm.Scene.from_params(st.params, fmt=args.fmt)
+    for f in range(args.warmup):
+        sc.integrate(depth[f], K, st.T_wc[f])
+        sc.raycast(K, st.T_wc[f], pts, nrm)
+    torch.cuda.synchronize()
+    s0 = sc.stats()
+    if not args.no_events:
+        sc.profile(True)
+        sc.profile_read()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        f = args.warmup + i
+        sc.integrate(depth[f], K, st.T_wc[f])
+        sc.raycast(K, st.T_wc[f], pts, nrm)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    prof = sc.profile_read() if not args.no_events else {}
+    s1 = sc.stats()
+    if args.calib_copy_mb > 0:
+        n = args.calib_copy_mb * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written")
+
+    vis_total = s1["n_visible_total"] - s0["n_visible_total"]
+    upd_total = s1["n_updated_total"] - s0["n_updated_total"]
+    voxels = vis_total * 512
+    rays = args.steps * W * H
+    kernels, best = {}, None
+    for name, (ms, launches) in prof.items():
+        if launches == 0:
+            continue
+        avg_ms = ms / launches
+        b = kernel_bytes(name, args.fmt, W, H, launches, vis_total, upd_total, s1["n_entries"])
+        gbs = b / (avg_ms * 1e-3) / 1e9
+        kernels[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": launches,
+                         "bytes_per_launch": round(b), "achieved_GBs": round(gbs, 1),
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        if best is None or ms > prof[best][0]:
+            best = name
+    roofline = None
+    if best:
+        k = kernels[best]
+        roofline = {"bound": "hbm", "kernel": best, "achieved": k["achieved_GBs"], "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": k["frac_hbm"], "traffic": None}
+    gpu_ms = sum(ms for ms, _ in prof.values()) if prof else None
+    out = {
+        "metric": METRIC,
+        "value": voxels / wall,
+        "unit": "voxels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.fmt,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {W}x{H} depth stream, frames "
+                               f"{args.warmup}..{args.warmup + args.steps - 1}, voxel "
+                               f"{p['voxel_size']} m, mu {p['mu']} m, 2^{int(np.log2(p['n_buckets']))} "
+                               f"buckets + 2^{int(np.log2(p['n_excess']))} excess, raycast {W}x{H}",
+                   "storage": args.fmt},
+        "rays_per_s": rays / wall,
+        "updated_voxels_per_s": upd_total / wall,
+        "visible_blocks_per_frame": vis_total / args.steps,
+        "gpu_kernel_ms_per_step": None if gpu_ms is None else gpu_ms / args.steps,
+        "kernels": kernels,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the host cores")
+        out["cpu_baseline"] = cpu_baseline(st, args.cpu_seconds)
+    sc.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

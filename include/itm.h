@@ -1,0 +1,161 @@
+/*
+ * itm.h -- C ABI of the gfx950 voxel-block-hashing TSDF fusion library (libitm.so).
+ *
+ * The library runs the per-frame hot path of volumetric depth fusion as described
+ * in "A Framework for the Volumetric Integration of Depth Images" (Prisacariu,
+ * Kaehler et al., 2014): allocation of 8^3 voxel blocks in a bucketed hash table
+ * with an excess list, a per-frame list of visible blocks, the truncated signed
+ * distance function (TSDF) update of every voxel of those blocks, and a raycast of
+ * the fused volume into point and normal maps.  Every step runs in HIP kernels on
+ * one GPU; no host fallback exists.
+ *
+ * Conventions shared by every call:
+ *   - metres; camera frame x right, y down, z forward; pinhole, no distortion;
+ *   - pixel (u, v) has its centre at integer coordinates (its camera ray is
+ *     ((u - cx) / fx, (v - cy) / fy, 1));
+ *   - T_wc: host array of 16 doubles, row-major 4x4 rigid camera-to-world transform
+ *     (the paper's M_d is its inverse); the library inverts it rigidly;
+ *   - voxel v (integer vector) sits at world position v * voxel_size; its block is
+ *     floor(v / 8) and its index inside the block is lx + 8 ly + 64 lz;
+ *   - F is the TSDF normalised by the truncation band mu, in [-1, 1]; W is the
+ *     number of fused observations, capped at max_w.
+ *
+ * Errors: every call returns a status (or NULL for create); the reason is in
+ * itm_last_error() (thread-local, valid until the next failing call on that
+ * thread).  No call aborts or exits.  Hash-table exhaustion is not an error: blocks
+ * that find no free entry are dropped and counted (itm_stats.n_dropped_total).
+ *
+ * Streams: integrate and raycast are asynchronous on the scene's HIP stream;
+ * export and get_stats synchronise it.  A scene must not be used from two host
+ * threads at once.
+ */
+#ifndef ITM_H
+#define ITM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct itm_scene itm_scene; /* opaque, owned by the library */
+
+typedef enum {
+    ITM_OK = 0,
+    ITM_ERR_ARG = -1,   /* invalid argument (NULL pointer, bad size, bad format) */
+    ITM_ERR_OOM = -2,   /* device or host allocation failed */
+    ITM_ERR_HIP = -3,   /* a HIP runtime call failed */
+    ITM_ERR_STATE = -4  /* call not valid in the scene's current state */
+} itm_status;
+
+/* Voxel storage forms (section "Framework Flexibility": the voxel type is a
+ * parameter of the volume).  Arithmetic is binary32 in every form.
+ *   ITM_VOX_F32   float F, float W (8 bytes per voxel)
+ *   ITM_VOX_F16   half F, half W (4 bytes per voxel)
+ *   ITM_VOX_S16U8 int16 F * 32767 (round to nearest even, clamped to +-32767),
+ *                 uint8 W (3 bytes per voxel; the paper's default voxel type) */
+typedef enum { ITM_VOX_F32 = 0, ITM_VOX_F16 = 1, ITM_VOX_S16U8 = 2 } itm_voxel_fmt;
+
+typedef struct {
+    double fx, fy, cx, cy; /* focal lengths and principal point, pixels */
+    int32_t width, height; /* image size, pixels */
+} itm_intrinsics;
+
+typedef struct {
+    int64_t n_allocated;     /* voxel blocks allocated so far */
+    int64_t n_visible_last;  /* visible blocks of the last integrated frame */
+    int64_t n_excess_used;   /* excess-list entries in use */
+    int64_t n_dropped_total; /* sum over frames of the distinct blocks dropped */
+    int64_t vba_capacity;    /* voxel block array capacity (blocks) */
+    int64_t n_updated_last;  /* voxels updated by the last integration */
+    int64_t n_entries;       /* hash entries: 2 * n_buckets + n_excess */
+    int64_t bytes_per_voxel; /* storage form's bytes per voxel */
+    int64_t n_visible_total; /* visible blocks summed over all integrations */
+    int64_t n_updated_total; /* updated voxels summed over all integrations */
+} itm_stats;
+
+/* Create a scene (section "Voxel Block Hashing"; scene parameters as in the
+ * paper's ITMSceneParams, section "Compilation, UI, Usage and Examples").
+ *   voxel_size  voxel edge, metres, > 0
+ *   mu          truncation band, metres, > 0
+ *   max_w       weight cap, >= 1 (<= 255 for ITM_VOX_S16U8, <= 2048 for ITM_VOX_F16)
+ *   n_buckets   hash buckets, a power of two (the hash is masked), each holding
+ *               2 entries ("a bucket of fixed size (typically 2)")
+ *   n_excess    entries of the unordered excess list, >= 0
+ * The voxel block array holds one block per hash entry (2 n_buckets + n_excess
+ * blocks), so block reservation never fails.  Voxels start at F = 1, W = 0.
+ * Storage F32, null stream, raycast depth range [0.2, 5.0] m.
+ * Returns NULL on failure (ITM_ERR_ARG / ITM_ERR_OOM / ITM_ERR_HIP reason). */
+itm_scene *itm_scene_create(float voxel_size, float mu, int32_t max_w, int64_t n_buckets,
+                            int64_t n_excess);
+
+/* As itm_scene_create, with the storage form, the HIP stream (hipStream_t, may be
+ * NULL) and the raycast search range in camera depth [z_near, z_far] metres. */
+itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_t n_buckets,
+                               int64_t n_excess, int32_t fmt, void *hip_stream, float z_near,
+                               float z_far);
+
+/* Free every device and host resource of the scene (synchronises its stream).
+ * NULL is ignored. */
+void itm_scene_destroy(itm_scene *scene);
+
+/* Replace the scene's HIP stream (hipStream_t, may be NULL). */
+itm_status itm_set_stream(itm_scene *scene, void *hip_stream);
+
+/* Fuse one depth frame: allocation (section "Allocation", stages one to three)
+ * then integration (section "Integration").
+ *   depth  DEVICE pointer, K->height * K->width float32, row-major, metres; a
+ *          pixel is valid when finite and > 0 (0, negative, NaN, inf = no data).
+ *          Read only; must stay valid until the stream reaches this work.
+ *   K      host pointer; width, height >= 3
+ *   T_wc   host pointer, 16 doubles (copied before return)
+ * Allocation: every voxel block crossed by a valid pixel's ray segment between
+ * camera depths max(d - mu, 0) and d + mu is looked up and inserted when absent
+ * (atomic insertion: every crossed block is allocated); the visible list of the
+ * frame is the set of those blocks.  Integration: every voxel of every visible
+ * block is projected into the depth image and updated with the paper's running
+ * average.  Asynchronous on the scene's stream. */
+itm_status itm_integrate(itm_scene *scene, const float *depth, const itm_intrinsics *K,
+                         const double *T_wc);
+
+/* Raycast the fused volume (section "Raycast") from pose T_wc.
+ *   out_pts, out_normals  DEVICE pointers, K->height * K->width float4 each
+ *   (16-byte aligned), written row-major in the world frame.  A hit pixel gets
+ *   (x, y, z, 1) and its unit normal (nx, ny, nz, 1) (w = 0 when the TSDF gradient
+ *   vanishes); a miss gets all zeros in both.
+ * The search covers camera depths [z_near, z_far] with the state machine of the
+ * paper (coarse block steps, fine steps of mu, steps of the TSDF value, two
+ * trilinear refinement steps behind the surface).  Asynchronous. */
+itm_status itm_raycast(itm_scene *scene, const itm_intrinsics *K, const double *T_wc,
+                       float *out_pts, float *out_normals);
+
+/* Copy the allocated blocks to the host, sorted ascending by (x, y, z).
+ *   coords  HOST int32[capacity * 3] or NULL to only count
+ *   sdf, w  HOST float[capacity * 512] each, or NULL; F as a float in [-1, 1] and
+ *           W as a float, voxel order lx + 8 ly + 64 lz
+ *   capacity  blocks the buffers hold; ITM_ERR_ARG when smaller than the count
+ *   n_blocks  HOST int64 out: number of allocated blocks
+ * Synchronises the stream. */
+itm_status itm_export_blocks(itm_scene *scene, int32_t *coords, float *sdf, float *w,
+                             int64_t capacity, int64_t *n_blocks);
+
+/* Counters of the scene (synchronises the stream). */
+itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
+
+/* Per-kernel timing with HIP events recorded on the scene's stream around every
+ * launch.  Kernel ids: 0 allocation, 1 visible-list compaction, 2 integration,
+ * 3 raycast. */
+#define ITM_KERNEL_COUNT 4
+itm_status itm_profile_enable(itm_scene *scene, int enable);
+/* Synchronises, then writes the summed milliseconds and launch counts per kernel
+ * id since profiling was enabled, and resets them. */
+itm_status itm_profile_read(itm_scene *scene, double *ms, int64_t *launches);
+
+/* Reason of the last failing call on this thread ("" if none). */
+const char *itm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ITM_H */

@@ -1,0 +1,252 @@
+"""Python binding of libitm.so, the gfx950 voxel-block-hashing TSDF fusion library.
+
+Argument marshalling only: every step of allocation, compaction, integration and
+raycasting runs in the library's HIP kernels.  Device buffers are torch tensors on
+the current HIP device; the library runs on torch's current stream.  The names
+mirror the C ABI in include/itm.h.  There is no fallback: if libitm.so is missing
+or no GPU is present, calls raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libitm.so")
+
+ITM_OK, ITM_ERR_ARG, ITM_ERR_OOM, ITM_ERR_HIP, ITM_ERR_STATE = 0, -1, -2, -3, -4
+ITM_VOX_F32, ITM_VOX_F16, ITM_VOX_S16U8 = 0, 1, 2
+FORMATS = {"f32": ITM_VOX_F32, "f16": ITM_VOX_F16, "s16u8": ITM_VOX_S16U8}
+KERNELS = ("alloc", "compact", "integrate", "raycast")
+ITM_KERNEL_COUNT = len(KERNELS)
+
+
+class ItmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"itm status {status}: {msg}")
+        self.status = status
+
+
+class itm_intrinsics(C.Structure):
+    _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class itm_stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("n_allocated", "n_visible_last", "n_excess_used",
+                                        "n_dropped_total", "vba_capacity", "n_updated_last",
+                                        "n_entries", "bytes_per_voxel", "n_visible_total",
+                                        "n_updated_total")]
+
+
+_lib = None
+_P = C.c_void_p
+EXPORTED = ("itm_scene_create", "itm_scene_create_ex", "itm_scene_destroy", "itm_set_stream",
+            "itm_integrate", "itm_raycast", "itm_export_blocks", "itm_get_stats",
+            "itm_profile_enable", "itm_profile_read", "itm_last_error")
+
+
+def lib():
+    """Load libitm.so (raises when it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1410_0925_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "itm_scene_create": (_P, [C.c_float, C.c_float, C.c_int32, C.c_int64, C.c_int64]),
+            "itm_scene_create_ex": (_P, [C.c_float, C.c_float, C.c_int32, C.c_int64, C.c_int64,
+                                         C.c_int32, _P, C.c_float, C.c_float]),
+            "itm_scene_destroy": (None, [_P]),
+            "itm_set_stream": (C.c_int, [_P, _P]),
+            "itm_integrate": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), _P]),
+            "itm_raycast": (C.c_int, [_P, C.POINTER(itm_intrinsics), _P, _P, _P]),
+            "itm_export_blocks": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+            "itm_get_stats": (C.c_int, [_P, C.POINTER(itm_stats)]),
+            "itm_profile_enable": (C.c_int, [_P, C.c_int]),
+            "itm_profile_read": (C.c_int, [_P, _P, _P]),
+            "itm_last_error": (C.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status):
+    if status != ITM_OK:
+        raise ItmError(status, lib().itm_last_error().decode())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _intr(K, width=None, height=None):
+    if isinstance(K, itm_intrinsics):
+        return K
+    fx, fy, cx, cy = K[:4]
+    w = width if width is not None else K[4]
+    h = height if height is not None else K[5]
+    return itm_intrinsics(float(fx), float(fy), float(cx), float(cy), int(w), int(h))
+
+
+def _pose(T):
+    T = np.ascontiguousarray(T, np.float64).reshape(16)
+    return T, T.ctypes.data_as(C.c_void_p)
+
+
+def _dev(t, dtype_name, numel):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a torch tensor on the GPU")
+    if str(t.dtype) != dtype_name or not t.is_contiguous() or t.numel() != numel:
+        raise ValueError(f"expected a contiguous {dtype_name} tensor of {numel} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------------------
+# C ABI mirrors
+# ---------------------------------------------------------------------------
+def itm_scene_create(voxel_size, mu, max_w, n_buckets, n_excess):
+    h = lib().itm_scene_create(voxel_size, mu, max_w, n_buckets, n_excess)
+    if not h:
+        raise ItmError(ITM_ERR_ARG, lib().itm_last_error().decode())
+    return h
+
+
+def itm_scene_create_ex(voxel_size, mu, max_w, n_buckets, n_excess, fmt=ITM_VOX_F32, stream=None,
+                        z_near=0.2, z_far=5.0):
+    h = lib().itm_scene_create_ex(voxel_size, mu, max_w, n_buckets, n_excess, fmt, stream,
+                                  z_near, z_far)
+    if not h:
+        raise ItmError(ITM_ERR_ARG, lib().itm_last_error().decode())
+    return h
+
+
+def itm_scene_destroy(h):
+    lib().itm_scene_destroy(h)
+
+
+def itm_set_stream(h, stream):
+    _check(lib().itm_set_stream(h, stream))
+
+
+def itm_integrate(h, depth, K, T_wc):
+    Ki = _intr(K)
+    ptr = _dev(depth, "torch.float32", Ki.width * Ki.height)
+    T, Tp = _pose(T_wc)
+    _check(lib().itm_integrate(h, ptr, C.byref(Ki), Tp))
+
+
+def itm_raycast(h, K, T_wc, out_pts, out_normals):
+    Ki = _intr(K)
+    n = Ki.width * Ki.height * 4
+    p = _dev(out_pts, "torch.float32", n)
+    q = _dev(out_normals, "torch.float32", n)
+    T, Tp = _pose(T_wc)
+    _check(lib().itm_raycast(h, C.byref(Ki), Tp, p, q))
+
+
+def itm_export_blocks(h, values=True):
+    n = C.c_int64(0)
+    _check(lib().itm_export_blocks(h, None, None, None, 0, C.byref(n)))
+    m = n.value
+    coords = np.empty((m, 3), np.int32)
+    sdf = np.empty((m, 512), np.float32) if values else None
+    w = np.empty((m, 512), np.float32) if values else None
+    _check(lib().itm_export_blocks(h, coords.ctypes.data_as(_P),
+                                   sdf.ctypes.data_as(_P) if values else None,
+                                   w.ctypes.data_as(_P) if values else None, m, C.byref(n)))
+    return coords, sdf, w
+
+
+def itm_get_stats(h):
+    st = itm_stats()
+    _check(lib().itm_get_stats(h, C.byref(st)))
+    return {name: getattr(st, name) for name, _ in itm_stats._fields_}
+
+
+def itm_profile_enable(h, enable=True):
+    _check(lib().itm_profile_enable(h, 1 if enable else 0))
+
+
+def itm_profile_read(h):
+    ms = np.zeros(ITM_KERNEL_COUNT, np.float64)
+    n = np.zeros(ITM_KERNEL_COUNT, np.int64)
+    _check(lib().itm_profile_read(h, ms.ctypes.data_as(_P), n.ctypes.data_as(_P)))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
+
+
+def itm_last_error():
+    return lib().itm_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+class Scene:
+    """A fused volume on the current GPU (owns the library scene)."""
+
+    def __init__(self, voxel_size, mu, max_w, n_buckets, n_excess, fmt="f32", z_near=0.2,
+                 z_far=5.0):
+        self.fmt = FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+        self.h = itm_scene_create_ex(voxel_size, mu, max_w, n_buckets, n_excess, self.fmt,
+                                     _stream(), z_near, z_far)
+        self.voxel_size, self.mu, self.max_w = voxel_size, mu, max_w
+
+    @classmethod
+    def from_params(cls, p, fmt="f32"):
+        return cls(p["voxel_size"], p["mu"], p["max_w"], p["n_buckets"], p["n_excess"], fmt=fmt)
+
+    def close(self):
+        if getattr(self, "h", None):
+            itm_scene_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _sync_stream(self):
+        _check(lib().itm_set_stream(self.h, _stream()))
+
+    def integrate(self, depth, K, T_wc):
+        self._sync_stream()
+        itm_integrate(self.h, depth, K, T_wc)
+
+    def raycast(self, K, T_wc, out_pts=None, out_normals=None):
+        import torch
+        Ki = _intr(K)
+        if out_pts is None:
+            out_pts = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
+        if out_normals is None:
+            out_normals = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
+        self._sync_stream()
+        itm_raycast(self.h, Ki, T_wc, out_pts, out_normals)
+        return out_pts, out_normals
+
+    def export(self, values=True):
+        self._sync_stream()
+        return itm_export_blocks(self.h, values)
+
+    def stats(self):
+        self._sync_stream()
+        return itm_get_stats(self.h)
+
+    def profile(self, enable=True):
+        itm_profile_enable(self.h, enable)
+
+    def profile_read(self):
+        self._sync_stream()
+        return itm_profile_read(self.h)

@@ -1,0 +1,225 @@
+// Integration (section "Integration", computeUpdatedVoxelDepthInfo) over the
+// voxels of the frame's visible blocks.
+//
+// One wave per visible block, grid-stride over the device-side visible count (no
+// host read-back).  Lane l owns voxels 4l..4l+3 and 256+4l..256+4l+3 of the block,
+// so every voxel load or store instruction of a wave covers one contiguous range
+// (16 B per lane in the float form).  A lane first decides, for its 8 voxels,
+// whether each is updated -- that needs only the voxel's position and the depth
+// image -- and reads and writes a group of 4 voxels only when one of them is.
+//
+// Decisions follow a fixed binary32 evaluation order (so that they can be
+// reproduced exactly): the block origin's camera coordinates are formed in binary64
+// once per block and split into a binary32 pair hi + lo; the in-block offset
+// (lx g_x + ly g_y) + lz g_z is added to lo first.  The value eta = d - p_z is
+// formed as (d - hi_z) - (lo_z + offset_z), accurate to ~1e-8 m at room scale.
+#include "itm_internal.hpp"
+
+namespace itm {
+
+template <int FMT>
+struct Group4;  // 4 consecutive voxels of one storage form
+
+template <>
+struct Group4<ITM_VOX_F32> {
+    float4 s, w;
+    __device__ void load(const void *sdf, const void *wt, int64_t i)
+    {
+        s = *reinterpret_cast<const float4 *>((const float *)sdf + i);
+        w = *reinterpret_cast<const float4 *>((const float *)wt + i);
+    }
+    __device__ void store(void *sdf, void *wt, int64_t i) const
+    {
+        *reinterpret_cast<float4 *>((float *)sdf + i) = s;
+        *reinterpret_cast<float4 *>((float *)wt + i) = w;
+    }
+    __device__ float F(int j) const { return j == 0 ? s.x : j == 1 ? s.y : j == 2 ? s.z : s.w; }
+    __device__ float Wv(int j) const { return j == 0 ? w.x : j == 1 ? w.y : j == 2 ? w.z : w.w; }
+    __device__ void set(int j, float f, float wv)
+    {
+        if (j == 0) { s.x = f; w.x = wv; }
+        else if (j == 1) { s.y = f; w.y = wv; }
+        else if (j == 2) { s.z = f; w.z = wv; }
+        else { s.w = f; w.w = wv; }
+    }
+};
+
+template <>
+struct Group4<ITM_VOX_F16> {
+    __half s[4], w[4];
+    __device__ void load(const void *sdf, const void *wt, int64_t i)
+    {
+        const uint2 a = *reinterpret_cast<const uint2 *>((const __half *)sdf + i);
+        const uint2 b = *reinterpret_cast<const uint2 *>((const __half *)wt + i);
+        __builtin_memcpy(s, &a, 8);
+        __builtin_memcpy(w, &b, 8);
+    }
+    __device__ void store(void *sdf, void *wt, int64_t i) const
+    {
+        uint2 a, b;
+        __builtin_memcpy(&a, s, 8);
+        __builtin_memcpy(&b, w, 8);
+        *reinterpret_cast<uint2 *>((__half *)sdf + i) = a;
+        *reinterpret_cast<uint2 *>((__half *)wt + i) = b;
+    }
+    __device__ float F(int j) const { return __half2float(s[j]); }
+    __device__ float Wv(int j) const { return __half2float(w[j]); }
+    __device__ void set(int j, float f, float wv)
+    {
+        s[j] = __float2half_rn(f);
+        w[j] = __float2half_rn(wv);
+    }
+};
+
+template <>
+struct Group4<ITM_VOX_S16U8> {
+    int16_t s[4];
+    uint8_t w[4];
+    __device__ void load(const void *sdf, const void *wt, int64_t i)
+    {
+        const uint2 a = *reinterpret_cast<const uint2 *>((const int16_t *)sdf + i);
+        const uint32_t b = *reinterpret_cast<const uint32_t *>((const uint8_t *)wt + i);
+        __builtin_memcpy(s, &a, 8);
+        __builtin_memcpy(w, &b, 4);
+    }
+    __device__ void store(void *sdf, void *wt, int64_t i) const
+    {
+        uint2 a;
+        uint32_t b;
+        __builtin_memcpy(&a, s, 8);
+        __builtin_memcpy(&b, w, 4);
+        *reinterpret_cast<uint2 *>((int16_t *)sdf + i) = a;
+        *reinterpret_cast<uint32_t *>((uint8_t *)wt + i) = b;
+    }
+    __device__ float F(int j) const { return Vox<ITM_VOX_S16U8>::to_f(s[j]); }
+    __device__ float Wv(int j) const { return (float)w[j]; }
+    __device__ void set(int j, float f, float wv)
+    {
+        s[j] = Vox<ITM_VOX_S16U8>::from_f(f);
+        w[j] = (uint8_t)wv;
+    }
+};
+
+template <int FMT>
+__global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a)
+{
+    const FrameGeom &g = a.fg;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt->set_used = 0;  // claim set drained by k_compact
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wave_in_wg = threadIdx.x / kWave;
+    const int waves_per_wg = blockDim.x / kWave;
+    const int n_vis = a.cnt->n_vis;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        a.cnt->n_vis_last = n_vis;
+        a.cnt->vis_total += (unsigned long long)n_vis;
+        if (a.host_hint) *(volatile int32_t *)a.host_hint = n_vis;  // sizes the next launch
+    }
+    const float mu = g.mu_f;
+    const float inv_mu = 1.0f / mu;
+    uint32_t n_upd = 0;
+
+    for (int bi = __builtin_amdgcn_readfirstlane(blockIdx.x * waves_per_wg + wave_in_wg); bi < n_vis;
+         bi += gridDim.x * waves_per_wg) {
+        const int32_t e = a.vis_list[bi];
+        unsigned long long key;
+        int32_t ptr;
+        if (e < 2 * a.h.n_buckets) {
+            key = a.h.buckets[e >> 1].key[e & 1];
+            ptr = a.h.buckets[e >> 1].ptr[e & 1];
+        } else {
+            key = a.h.excess[e - 2 * a.h.n_buckets].key;
+            ptr = a.h.excess[e - 2 * a.h.n_buckets].ptr;
+        }
+        if (ptr < 0) continue;  // cannot happen: every flagged entry owns a block
+        int kx, ky, kz;
+        unpack_key(key, kx, ky, kz);
+        // block origin in camera coordinates, binary64 -> binary32 pair
+        const double o0 = (double)(8 * kx) * g.s, o1 = (double)(8 * ky) * g.s,
+                     o2 = (double)(8 * kz) * g.s;
+        float hi[3], lo[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            double w = g.Rcw[3 * c + 0] * o0;
+            w = w + g.Rcw[3 * c + 1] * o1;
+            w = w + g.Rcw[3 * c + 2] * o2;
+            w = w + g.tcw[c];
+            hi[c] = (float)w;
+            lo[c] = (float)(w - (double)hi[c]);
+        }
+        const int64_t vbase = (int64_t)ptr * kBlockVox;
+#pragma unroll
+        for (int grp = 0; grp < 2; grp++) {
+            const int li0 = 4 * lane + 256 * grp;
+            const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
+            float eta[4];
+            uint32_t upd = 0;
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float fx_ = (float)((li0 & 7) + j);
+                float p[3], dl2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    float t = fx_ * g.g[0][c];
+                    t = t + fy_ * g.g[1][c];
+                    t = t + fz_ * g.g[2][c];
+                    p[c] = hi[c] + (lo[c] + t);
+                    if (c == 2) dl2 = t;
+                }
+                eta[j] = 0.0f;
+                if (p[2] <= 0.0f) continue;
+                const float x = g.fx * p[0] / p[2] + g.cx;
+                const float y = g.fy * p[1] / p[2] + g.cy;
+                if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
+                const float d = a.depth[(int)(x + 0.5f) + (int)(y + 0.5f) * g.W];
+                if (!(d > 0.0f) || isinf(d)) continue;
+                const float e32 = (d - hi[2]) - (lo[2] + dl2);
+                if (e32 < -mu) continue;
+                eta[j] = e32;
+                upd |= 1u << j;
+            }
+            if (upd) {
+                Group4<FMT> v;
+                v.load(a.sdf, a.w, vbase + li0);
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (!(upd & (1u << j))) continue;
+                    const float f = fminf(1.0f, eta[j] * inv_mu);
+                    const float F = v.F(j), W = v.Wv(j);
+                    const float Wn = W + 1.0f;
+                    // running average F <- (W F + f) / (W + 1), in incremental form
+                    const float Fn = F + (f - F) / Wn;
+                    v.set(j, Fn, fminf(Wn, g.max_w_f));
+                }
+                v.store(a.sdf, a.w, vbase + li0);
+                n_upd += __builtin_popcount(upd);
+            }
+        }
+    }
+    // one counter update per workgroup, on one of kStripes separate lines
+    __shared__ uint32_t wave_upd[256 / kWave];
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) n_upd += __shfl_xor(n_upd, o, kWave);
+    if (lane == 0) wave_upd[wave_in_wg] = n_upd;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < waves_per_wg; w++) t += wave_upd[w];
+        if (t) {
+            const int sI = blockIdx.x % kStripes;
+            atomicAdd(&a.cnt->upd[0][sI][0], t);
+            atomicAdd(&a.cnt->upd[1][sI][0], t);
+        }
+    }
+}
+
+hipError_t launch_integrate(int fmt, const IntegrateArgs &a, int grid, hipStream_t st)
+{
+    switch (fmt) {
+    case ITM_VOX_F32: k_integrate<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
+    case ITM_VOX_F16: k_integrate<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;
+    default: k_integrate<ITM_VOX_S16U8><<<grid, 256, 0, st>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace itm

@@ -1,0 +1,228 @@
+// Internal device-side definitions shared by the library's kernels.
+//
+// HBM layout of a scene (one allocation each):
+//   buckets  n_buckets x 32 B   {key[2] (u64), ptr[2] (i32), head (i32), pad}
+//            the ordered part of the hash table, 2 entries per bucket; `head` is the
+//            first excess entry of the bucket's chain (-1 = none), i.e. the offset
+//            the paper keeps in the bucket's last entry
+//   excess   n_excess x 16 B    {key (u64), ptr (i32), next (i32)}  unordered part
+//   vis      n_entries bytes    per-entry visibility flag of the current frame
+//   vis_list n_entries x i32    compacted visible entry ids
+//   sdf, w   capacity x 512     voxel block array, structure of arrays, one
+//                               element type per storage form
+//   set      R x u64            per-frame set of blocks claimed for the excess list
+//   cnt      Counters           device counters
+// Entry ids follow the paper's layout: 2 b + i for slot i of bucket b, then
+// 2 n_buckets + x for excess entry x.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <climits>
+#include <stdint.h>
+
+#include "itm.h"
+
+namespace itm {
+
+constexpr int kBlockVox = 512;
+constexpr unsigned long long kKeyValid = 1ull << 63;
+constexpr int kWave = 64;
+constexpr int kStripes = 32;
+
+struct alignas(32) Bucket {
+    unsigned long long key[2];
+    int32_t ptr[2];
+    int32_t head;
+    int32_t pad;
+};
+static_assert(sizeof(Bucket) == 32, "bucket record is 32 bytes");
+
+struct alignas(16) Excess {
+    unsigned long long key;
+    int32_t ptr;
+    int32_t next;
+};
+static_assert(sizeof(Excess) == 16, "excess record is 16 bytes");
+
+struct Counters {
+    int32_t vba_next;     // voxel blocks handed out (bump allocator = free stack pop)
+    int32_t excess_next;  // excess entries handed out (may run past n_excess)
+    int32_t n_vis;        // visible entries of the current frame
+    int32_t set_used;     // claim-set slots used in the current frame
+    unsigned long long dropped_total;
+    int32_t n_vis_last;   // visible count of the last completed integration
+    int32_t pad;
+    unsigned long long vis_total;  // visible blocks summed over all integrations
+    unsigned long long pad2[4];
+    // updated-voxel counts, striped over separate 128-byte lines so that the
+    // per-workgroup additions do not all hit one address: [frame][stripe] for
+    // the current frame (cleared by k_alloc), [total][stripe] since creation
+    unsigned long long upd[2][kStripes][16];
+};
+
+struct HashView {
+    Bucket *buckets;
+    Excess *excess;
+    uint32_t mask;
+    int32_t n_buckets;
+    int32_t n_excess;
+};
+
+// block key: valid bit | x | y << 16 | z << 32 (16-bit two's complement each)
+__device__ __forceinline__ unsigned long long pack_key(int x, int y, int z)
+{
+    return kKeyValid | (unsigned long long)(uint16_t)x | ((unsigned long long)(uint16_t)y << 16) |
+           ((unsigned long long)(uint16_t)z << 32);
+}
+
+__device__ __forceinline__ void unpack_key(unsigned long long k, int &x, int &y, int &z)
+{
+    x = (int16_t)(k & 0xffffu);
+    y = (int16_t)((k >> 16) & 0xffffu);
+    z = (int16_t)((k >> 32) & 0xffffu);
+}
+
+__device__ __forceinline__ bool in_key_range(int x, int y, int z)
+{
+    return x >= -32768 && x <= 32767 && y >= -32768 && y <= 32767 && z >= -32768 && z <= 32767;
+}
+
+// hashIndex of section "Hash Table and Hashing Function": unsigned 32-bit products
+// of the coordinates with three primes, xor-ed, masked to the bucket count
+__device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mask)
+{
+    return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u)) & mask;
+}
+
+// Read-only retrieval (section "Hash Table Operations"): the bucket's two
+// entries, then the excess chain.  Returns the voxel block pointer or -1.
+__device__ __forceinline__ int32_t find_block(const HashView &h, int x, int y, int z)
+{
+    if (!in_key_range(x, y, z)) return -1;
+    const unsigned long long key = pack_key(x, y, z);
+    const Bucket *B = h.buckets + hash_index(x, y, z, h.mask);
+    const ulonglong2 keys = *reinterpret_cast<const ulonglong2 *>(B->key);
+    const int4 rest = *reinterpret_cast<const int4 *>(&B->ptr[0]);  // ptr0, ptr1, head, pad
+    if (keys.x == key) return rest.x;
+    if (keys.y == key) return rest.y;
+    int32_t x_i = rest.z;
+    while (x_i >= 0) {
+        const Excess E = h.excess[x_i];
+        if (E.key == key) return E.ptr;
+        x_i = E.next;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// voxel storage forms
+// ---------------------------------------------------------------------------
+template <int FMT>
+struct Vox;
+
+template <>
+struct Vox<ITM_VOX_F32> {
+    using S = float;
+    using Wt = float;
+    static constexpr int bytes = 8;
+    __device__ static float to_f(float s) { return s; }
+    __device__ static float from_f(float f) { return f; }
+    __device__ static float w_to_f(float w) { return w; }
+    __device__ static float w_from_f(float w) { return w; }
+};
+
+template <>
+struct Vox<ITM_VOX_F16> {
+    using S = __half;
+    using Wt = __half;
+    static constexpr int bytes = 4;
+    __device__ static float to_f(__half s) { return __half2float(s); }
+    __device__ static __half from_f(float f) { return __float2half_rn(f); }
+    __device__ static float w_to_f(__half w) { return __half2float(w); }
+    __device__ static __half w_from_f(float w) { return __float2half_rn(w); }
+};
+
+template <>
+struct Vox<ITM_VOX_S16U8> {
+    using S = int16_t;
+    using Wt = uint8_t;
+    static constexpr int bytes = 3;
+    __device__ static float to_f(int16_t s) { return (float)s * (1.0f / 32767.0f); }
+    __device__ static int16_t from_f(float f)
+    {
+        float q = rintf(f * 32767.0f);
+        q = fminf(fmaxf(q, -32767.0f), 32767.0f);
+        return (int16_t)q;
+    }
+    __device__ static float w_to_f(uint8_t w) { return (float)w; }
+    __device__ static uint8_t w_from_f(float w) { return (uint8_t)w; }
+};
+
+// ---------------------------------------------------------------------------
+// kernel argument blocks
+// ---------------------------------------------------------------------------
+struct FrameGeom {
+    // camera
+    int32_t W, H;
+    float fx, fy, cx, cy;               // binary32 copies for the projection decision
+    double fxd, fyd, cxd, cyd, inv_fx, inv_fy;
+    double Rwc[9], twc[3];
+    double Rcw[9], tcw[3];
+    float g[3][3];                      // g[j][a]: camera-frame step of one voxel along world axis j
+    // scene
+    double s, inv_bs;                   // voxel size, 1 / (8 s)
+    float s_f, mu_f, max_w_f;
+    double mu;
+    float z_near, z_far;
+};
+
+struct AllocArgs {
+    FrameGeom fg;
+    const float *depth;
+    HashView h;
+    uint8_t *vis;
+    unsigned long long *set;
+    int32_t *set_list;
+    uint32_t set_mask;
+    Counters *cnt;
+};
+
+struct CompactArgs {
+    uint4 *vis4;
+    int32_t n_chunks;
+    int32_t *vis_list;
+    unsigned long long *set;
+    const int32_t *set_list;
+    Counters *cnt;
+};
+
+struct IntegrateArgs {
+    FrameGeom fg;
+    const float *depth;
+    HashView h;
+    const int32_t *vis_list;
+    void *sdf;
+    void *w;
+    Counters *cnt;
+    int32_t *host_hint;   // mapped pinned host word: visible count (may be null)
+};
+
+struct RaycastArgs {
+    FrameGeom fg;
+    HashView h;
+    const void *sdf;
+    float4 *pts;
+    float4 *nrm;
+};
+
+// launchers (one translation unit each)
+hipError_t launch_alloc(const AllocArgs &a, hipStream_t st);
+hipError_t launch_compact(const CompactArgs &a, int grid, hipStream_t st);
+hipError_t launch_integrate(int fmt, const IntegrateArgs &a, int grid, hipStream_t st);
+hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st);
+hipError_t launch_init(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_t *vis, int64_t nvis,
+                       unsigned long long *set, int64_t nset, Counters *cnt, int fmt, void *sdf,
+                       void *w, int64_t n_vox, hipStream_t st);
+
+}  // namespace itm

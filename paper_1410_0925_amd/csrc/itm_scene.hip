@@ -1,0 +1,520 @@
+// Host side of the C ABI declared in include/itm.h: scene lifetime, per-frame
+// launch sequence, export, statistics and per-kernel event timing.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <new>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "itm_internal.hpp"
+
+using namespace itm;
+
+namespace {
+
+thread_local std::string g_err;
+
+itm_status fail(itm_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+itm_status fail(itm_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(ITM_ERR_HIP, "%s failed: %s", #call, hipGetErrorString(e_));         \
+    } while (0)
+
+int64_t next_pow2(int64_t x)
+{
+    int64_t p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+constexpr int kProfSlots = 4096;
+
+}  // namespace
+
+struct itm_scene {
+    float s, mu;
+    int32_t max_w;
+    int64_t n_buckets, n_excess, n_entries, vba_cap, set_size;
+    uint32_t mask;
+    int fmt;
+    float z_near, z_far;
+    hipStream_t stream;
+    int device, num_cu;
+
+    Bucket *buckets = nullptr;
+    Excess *excess = nullptr;
+    uint8_t *vis = nullptr;
+    int64_t vis_bytes = 0;
+    int32_t *vis_list = nullptr;
+    void *sdf = nullptr;
+    void *w = nullptr;
+    unsigned long long *set = nullptr;
+    int32_t *set_list = nullptr;
+    Counters *cnt = nullptr;
+    int32_t *hint_host = nullptr;  // mapped pinned word written by k_compact
+    int32_t *hint_dev = nullptr;
+
+    bool prof = false;
+    std::vector<hipEvent_t> ev;     // 2 per slot
+    std::vector<int> ev_kernel;
+    int ev_used = 0;
+    double prof_ms[ITM_KERNEL_COUNT] = {};
+    int64_t prof_n[ITM_KERNEL_COUNT] = {};
+};
+
+namespace {
+
+size_t sdf_elem(int fmt) { return fmt == ITM_VOX_F32 ? 4 : 2; }
+size_t w_elem(int fmt) { return fmt == ITM_VOX_F32 ? 4 : fmt == ITM_VOX_F16 ? 2 : 1; }
+
+void release(itm_scene *sc)
+{
+    if (!sc) return;
+    (void)hipStreamSynchronize(sc->stream);
+    for (hipEvent_t e : sc->ev) (void)hipEventDestroy(e);
+    (void)hipFree(sc->buckets);
+    (void)hipFree(sc->excess);
+    (void)hipFree(sc->vis);
+    (void)hipFree(sc->vis_list);
+    (void)hipFree(sc->sdf);
+    (void)hipFree(sc->w);
+    (void)hipFree(sc->set);
+    (void)hipFree(sc->set_list);
+    (void)hipFree(sc->cnt);
+    if (sc->hint_host) (void)hipHostFree(sc->hint_host);
+    delete sc;
+}
+
+itm_status dev_alloc(void **p, size_t bytes, const char *what)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 16);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? ITM_ERR_OOM : ITM_ERR_HIP, "hipMalloc(%s, %zu bytes): %s",
+                    what, bytes, hipGetErrorString(e));
+    }
+    return ITM_OK;
+}
+
+// camera + scene geometry for one call; binary64 values formed on the host in the
+// same fixed order the decisions are specified in
+itm_status make_geom(const itm_scene *sc, const itm_intrinsics *K, const double *T, FrameGeom *g)
+{
+    if (!K || !T) return fail(ITM_ERR_ARG, "NULL intrinsics or pose");
+    if (K->width < 3 || K->height < 3 || K->width > 32768 || K->height > 32768)
+        return fail(ITM_ERR_ARG, "image size %dx%d out of range", K->width, K->height);
+    if (!(K->fx > 0) || !(K->fy > 0) || !std::isfinite(K->cx) || !std::isfinite(K->cy))
+        return fail(ITM_ERR_ARG, "invalid intrinsics");
+    for (int i = 0; i < 16; i++)
+        if (!std::isfinite(T[i])) return fail(ITM_ERR_ARG, "non-finite pose");
+    std::memset(g, 0, sizeof *g);
+    g->W = K->width;
+    g->H = K->height;
+    g->fxd = K->fx; g->fyd = K->fy; g->cxd = K->cx; g->cyd = K->cy;
+    g->fx = (float)K->fx; g->fy = (float)K->fy; g->cx = (float)K->cx; g->cy = (float)K->cy;
+    g->inv_fx = 1.0 / K->fx;
+    g->inv_fy = 1.0 / K->fy;
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) g->Rwc[3 * i + j] = T[4 * i + j];
+        g->twc[i] = T[4 * i + 3];
+    }
+    // rigid inverse: R_cw = R_wc^T, t_cw = -R_wc^T t_wc
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) g->Rcw[3 * i + j] = g->Rwc[3 * j + i];
+        double acc = g->Rwc[0 * 3 + i] * g->twc[0];
+        acc = acc + g->Rwc[1 * 3 + i] * g->twc[1];
+        acc = acc + g->Rwc[2 * 3 + i] * g->twc[2];
+        g->tcw[i] = -acc;
+    }
+    g->s = (double)sc->s;
+    g->inv_bs = 1.0 / (8.0 * g->s);
+    for (int j = 0; j < 3; j++)
+        for (int a = 0; a < 3; a++) g->g[j][a] = (float)(g->Rcw[3 * a + j] * g->s);
+    g->s_f = sc->s;
+    g->mu_f = sc->mu;
+    g->mu = (double)sc->mu;
+    g->max_w_f = (float)sc->max_w;
+    g->z_near = sc->z_near;
+    g->z_far = sc->z_far;
+    return ITM_OK;
+}
+
+HashView hash_view(const itm_scene *sc)
+{
+    HashView h;
+    h.buckets = sc->buckets;
+    h.excess = sc->excess;
+    h.mask = sc->mask;
+    h.n_buckets = (int32_t)sc->n_buckets;
+    h.n_excess = (int32_t)sc->n_excess;
+    return h;
+}
+
+itm_status prof_flush(itm_scene *sc)
+{
+    if (sc->ev_used == 0) return ITM_OK;
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    for (int i = 0; i < sc->ev_used; i++) {
+        float ms = 0;
+        HIP_TRY(hipEventElapsedTime(&ms, sc->ev[2 * i], sc->ev[2 * i + 1]));
+        sc->prof_ms[sc->ev_kernel[i]] += ms;
+        sc->prof_n[sc->ev_kernel[i]] += 1;
+    }
+    sc->ev_used = 0;
+    return ITM_OK;
+}
+
+// record events around one launch when profiling is on
+struct ProfScope {
+    itm_scene *sc;
+    int slot = -1;
+    ProfScope(itm_scene *s, int kernel) : sc(s)
+    {
+        if (!sc->prof) return;
+        if (sc->ev_used == kProfSlots && prof_flush(sc) != ITM_OK) return;
+        slot = sc->ev_used++;
+        sc->ev_kernel[slot] = kernel;
+        (void)hipEventRecord(sc->ev[2 * slot], sc->stream);
+    }
+    ~ProfScope()
+    {
+        if (slot >= 0) (void)hipEventRecord(sc->ev[2 * slot + 1], sc->stream);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+const char *itm_last_error(void) { return g_err.c_str(); }
+
+itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_t n_buckets,
+                               int64_t n_excess, int32_t fmt, void *hip_stream, float z_near,
+                               float z_far)
+{
+    if (!(voxel_size > 0) || !std::isfinite(voxel_size) || !(mu > 0) || !std::isfinite(mu)) {
+        fail(ITM_ERR_ARG, "voxel_size and mu must be finite and > 0");
+        return nullptr;
+    }
+    if (fmt != ITM_VOX_F32 && fmt != ITM_VOX_F16 && fmt != ITM_VOX_S16U8) {
+        fail(ITM_ERR_ARG, "unknown voxel format %d", fmt);
+        return nullptr;
+    }
+    const int32_t wmax = fmt == ITM_VOX_S16U8 ? 255 : fmt == ITM_VOX_F16 ? 2048 : (1 << 24);
+    if (max_w < 1 || max_w > wmax) {
+        fail(ITM_ERR_ARG, "max_w %d out of range [1, %d] for this voxel format", max_w, wmax);
+        return nullptr;
+    }
+    if (n_buckets < 1 || (n_buckets & (n_buckets - 1)) != 0 || n_buckets > (int64_t(1) << 28)) {
+        fail(ITM_ERR_ARG, "n_buckets must be a power of two in [1, 2^28]");
+        return nullptr;
+    }
+    if (n_excess < 0 || n_excess > (int64_t(1) << 28)) {
+        fail(ITM_ERR_ARG, "n_excess must be in [0, 2^28]");
+        return nullptr;
+    }
+    if (!(z_near > 0) || !(z_far > z_near) || !std::isfinite(z_far)) {
+        fail(ITM_ERR_ARG, "raycast range must satisfy 0 < z_near < z_far < inf");
+        return nullptr;
+    }
+    itm_scene *sc = new (std::nothrow) itm_scene();
+    if (!sc) {
+        fail(ITM_ERR_OOM, "host allocation failed");
+        return nullptr;
+    }
+    sc->s = voxel_size;
+    sc->mu = mu;
+    sc->max_w = max_w;
+    sc->n_buckets = n_buckets;
+    sc->n_excess = n_excess;
+    sc->n_entries = 2 * n_buckets + n_excess;
+    sc->vba_cap = sc->n_entries;
+    sc->mask = (uint32_t)(n_buckets - 1);
+    sc->fmt = fmt;
+    sc->z_near = z_near;
+    sc->z_far = z_far;
+    sc->stream = (hipStream_t)hip_stream;
+    // claim set: holds every distinct block claimed for the excess list in one
+    // frame at load <= 1/2 (a VGA frame crosses ~1e4 distinct blocks)
+    sc->set_size = std::min<int64_t>(next_pow2(std::max<int64_t>(2 * n_excess, 1 << 16)), 1 << 24);
+    if (hipGetDevice(&sc->device) != hipSuccess) {
+        fail(ITM_ERR_HIP, "no HIP device");
+        release(sc);
+        return nullptr;
+    }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, sc->device) != hipSuccess) {
+        fail(ITM_ERR_HIP, "hipGetDeviceProperties failed");
+        release(sc);
+        return nullptr;
+    }
+    sc->num_cu = prop.multiProcessorCount;
+    const int64_t n_vox = sc->vba_cap * kBlockVox;
+    sc->vis_bytes = (sc->n_entries + 15) / 16 * 16;
+    if (dev_alloc((void **)&sc->buckets, sizeof(Bucket) * n_buckets, "buckets") ||
+        dev_alloc((void **)&sc->excess, sizeof(Excess) * std::max<int64_t>(n_excess, 1), "excess") ||
+        dev_alloc((void **)&sc->vis, sc->vis_bytes, "vis") ||
+        dev_alloc((void **)&sc->vis_list, sizeof(int32_t) * sc->n_entries, "vis_list") ||
+        dev_alloc(&sc->sdf, sdf_elem(fmt) * n_vox, "sdf") ||
+        dev_alloc(&sc->w, w_elem(fmt) * n_vox, "weights") ||
+        dev_alloc((void **)&sc->set, sizeof(unsigned long long) * sc->set_size, "claim set") ||
+        dev_alloc((void **)&sc->set_list, sizeof(int32_t) * sc->set_size, "claim list") ||
+        dev_alloc((void **)&sc->cnt, sizeof(Counters), "counters")) {
+        release(sc);
+        return nullptr;
+    }
+    if (hipHostMalloc((void **)&sc->hint_host, sizeof(int32_t), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&sc->hint_dev, sc->hint_host, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        sc->hint_host = nullptr;
+        sc->hint_dev = nullptr;
+    } else {
+        *sc->hint_host = 0;
+    }
+    hipError_t e = launch_init(sc->buckets, n_buckets, sc->excess, n_excess, sc->vis, sc->vis_bytes,
+                               sc->set, sc->set_size, sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    if (e != hipSuccess) {
+        fail(ITM_ERR_HIP, "scene initialisation failed: %s", hipGetErrorString(e));
+        release(sc);
+        return nullptr;
+    }
+    return sc;
+}
+
+itm_scene *itm_scene_create(float voxel_size, float mu, int32_t max_w, int64_t n_buckets,
+                            int64_t n_excess)
+{
+    return itm_scene_create_ex(voxel_size, mu, max_w, n_buckets, n_excess, ITM_VOX_F32, nullptr, 0.2f,
+                               5.0f);
+}
+
+void itm_scene_destroy(itm_scene *sc) { release(sc); }
+
+itm_status itm_set_stream(itm_scene *sc, void *hip_stream)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    sc->stream = (hipStream_t)hip_stream;
+    return ITM_OK;
+}
+
+itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics *K, const double *T_wc)
+{
+    if (!sc || !depth) return fail(ITM_ERR_ARG, "NULL scene or depth");
+    FrameGeom g;
+    if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
+    const HashView h = hash_view(sc);
+    {
+        ProfScope ps(sc, 0);
+        AllocArgs a;
+        a.fg = g;
+        a.depth = depth;
+        a.h = h;
+        a.vis = sc->vis;
+        a.set = sc->set;
+        a.set_list = sc->set_list;
+        a.set_mask = (uint32_t)(sc->set_size - 1);
+        a.cnt = sc->cnt;
+        HIP_TRY(launch_alloc(a, sc->stream));
+    }
+    {
+        ProfScope ps(sc, 1);
+        CompactArgs c;
+        c.vis4 = reinterpret_cast<uint4 *>(sc->vis);
+        c.n_chunks = (int32_t)(sc->vis_bytes / 16);
+        c.vis_list = sc->vis_list;
+        c.set = sc->set;
+        c.set_list = sc->set_list;
+        c.cnt = sc->cnt;
+        const int grid = (int)std::min<int64_t>((c.n_chunks + 1023) / 1024, (int64_t)sc->num_cu * 8);
+        HIP_TRY(launch_compact(c, std::max(grid, 1), sc->stream));
+    }
+    {
+        ProfScope ps(sc, 2);
+        IntegrateArgs ia;
+        ia.fg = g;
+        ia.depth = depth;
+        ia.h = h;
+        ia.vis_list = sc->vis_list;
+        ia.sdf = sc->sdf;
+        ia.w = sc->w;
+        ia.cnt = sc->cnt;
+        ia.host_hint = sc->hint_dev;
+        // grid-stride over the device-side count; the size follows the last known
+        // visible count (4 blocks per workgroup), at least one workgroup per CU
+        int64_t last = sc->hint_host ? *(volatile int32_t *)sc->hint_host : 0;
+        int64_t grid = std::max<int64_t>((last + last / 4 + 3) / 4, (int64_t)sc->num_cu * 2);
+        grid = std::min<int64_t>(grid, (int64_t)sc->num_cu * 64);
+        HIP_TRY(launch_integrate(sc->fmt, ia, (int)grid, sc->stream));
+    }
+    return ITM_OK;
+}
+
+itm_status itm_raycast(itm_scene *sc, const itm_intrinsics *K, const double *T_wc, float *out_pts,
+                       float *out_normals)
+{
+    if (!sc || !out_pts || !out_normals) return fail(ITM_ERR_ARG, "NULL scene or output");
+    if (((uintptr_t)out_pts | (uintptr_t)out_normals) & 15u)
+        return fail(ITM_ERR_ARG, "outputs must be 16-byte aligned");
+    FrameGeom g;
+    if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
+    ProfScope ps(sc, 3);
+    RaycastArgs a;
+    a.fg = g;
+    a.h = hash_view(sc);
+    a.sdf = sc->sdf;
+    a.pts = reinterpret_cast<float4 *>(out_pts);
+    a.nrm = reinterpret_cast<float4 *>(out_normals);
+    HIP_TRY(launch_raycast(sc->fmt, a, sc->stream));
+    return ITM_OK;
+}
+
+itm_status itm_get_stats(itm_scene *sc, itm_stats *out)
+{
+    if (!sc || !out) return fail(ITM_ERR_ARG, "NULL argument");
+    Counters c;
+    HIP_TRY(hipMemcpyAsync(&c, sc->cnt, sizeof c, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    out->n_allocated = std::min<int64_t>(c.vba_next, sc->vba_cap);
+    out->n_visible_last = c.n_vis_last;
+    out->n_excess_used = std::min<int64_t>(c.excess_next, sc->n_excess);
+    out->n_dropped_total = (int64_t)c.dropped_total;
+    out->vba_capacity = sc->vba_cap;
+    unsigned long long u_last = 0, u_tot = 0;
+    for (int i = 0; i < kStripes; i++) {
+        u_last += c.upd[0][i][0];
+        u_tot += c.upd[1][i][0];
+    }
+    out->n_updated_last = (int64_t)u_last;
+    out->n_entries = sc->n_entries;
+    out->bytes_per_voxel = (int64_t)(sdf_elem(sc->fmt) + w_elem(sc->fmt));
+    out->n_visible_total = (int64_t)c.vis_total;
+    out->n_updated_total = (int64_t)u_tot;
+    return ITM_OK;
+}
+
+itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *w, int64_t capacity,
+                             int64_t *n_blocks)
+{
+    if (!sc || !n_blocks) return fail(ITM_ERR_ARG, "NULL scene or n_blocks");
+    std::vector<Bucket> hb(sc->n_buckets);
+    std::vector<Excess> hx(std::max<int64_t>(sc->n_excess, 1));
+    HIP_TRY(hipMemcpyAsync(hb.data(), sc->buckets, sizeof(Bucket) * sc->n_buckets, hipMemcpyDeviceToHost,
+                           sc->stream));
+    if (sc->n_excess)
+        HIP_TRY(hipMemcpyAsync(hx.data(), sc->excess, sizeof(Excess) * sc->n_excess, hipMemcpyDeviceToHost,
+                               sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    struct Rec { int32_t x, y, z, ptr; };
+    std::vector<Rec> recs;
+    auto add = [&](unsigned long long k, int32_t p) {
+        if (!(k & kKeyValid) || p < 0) return;
+        Rec r;
+        r.x = (int16_t)(k & 0xffff);
+        r.y = (int16_t)((k >> 16) & 0xffff);
+        r.z = (int16_t)((k >> 32) & 0xffff);
+        r.ptr = p;
+        recs.push_back(r);
+    };
+    for (const Bucket &b : hb) { add(b.key[0], b.ptr[0]); add(b.key[1], b.ptr[1]); }
+    for (int64_t i = 0; i < sc->n_excess; i++) add(hx[i].key, hx[i].ptr);
+    std::sort(recs.begin(), recs.end(), [](const Rec &a, const Rec &b) {
+        if (a.x != b.x) return a.x < b.x;
+        if (a.y != b.y) return a.y < b.y;
+        return a.z < b.z;
+    });
+    *n_blocks = (int64_t)recs.size();
+    if (!coords && !sdf && !w) return ITM_OK;
+    if (capacity < (int64_t)recs.size())
+        return fail(ITM_ERR_ARG, "capacity %lld < %zu blocks", (long long)capacity, recs.size());
+    const int32_t n_used = recs.empty() ? 0 : std::max_element(recs.begin(), recs.end(), [](const Rec &a, const Rec &b) {
+                                                   return a.ptr < b.ptr;
+                                               })->ptr + 1;
+    std::vector<uint8_t> hs, hw;
+    if (sdf) hs.resize(sdf_elem(sc->fmt) * kBlockVox * (size_t)n_used);
+    if (w) hw.resize(w_elem(sc->fmt) * kBlockVox * (size_t)n_used);
+    if (sdf && n_used)
+        HIP_TRY(hipMemcpyAsync(hs.data(), sc->sdf, hs.size(), hipMemcpyDeviceToHost, sc->stream));
+    if (w && n_used) HIP_TRY(hipMemcpyAsync(hw.data(), sc->w, hw.size(), hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    for (size_t i = 0; i < recs.size(); i++) {
+        const Rec &r = recs[i];
+        if (coords) { coords[3 * i] = r.x; coords[3 * i + 1] = r.y; coords[3 * i + 2] = r.z; }
+        const size_t src = (size_t)r.ptr * kBlockVox;
+        for (int l = 0; l < kBlockVox; l++) {
+            if (sdf) {
+                float f;
+                if (sc->fmt == ITM_VOX_F32) std::memcpy(&f, &hs[4 * (src + l)], 4);
+                else if (sc->fmt == ITM_VOX_F16) {
+                    __half hv;
+                    std::memcpy(&hv, &hs[2 * (src + l)], 2);
+                    f = __half2float(hv);
+                } else {
+                    int16_t q;
+                    std::memcpy(&q, &hs[2 * (src + l)], 2);
+                    f = (float)q / 32767.0f;
+                }
+                sdf[i * kBlockVox + l] = f;
+            }
+            if (w) {
+                float wf;
+                if (sc->fmt == ITM_VOX_F32) std::memcpy(&wf, &hw[4 * (src + l)], 4);
+                else if (sc->fmt == ITM_VOX_F16) {
+                    __half hv;
+                    std::memcpy(&hv, &hw[2 * (src + l)], 2);
+                    wf = __half2float(hv);
+                } else wf = (float)hw[src + l];
+                w[i * kBlockVox + l] = wf;
+            }
+        }
+    }
+    return ITM_OK;
+}
+
+itm_status itm_profile_enable(itm_scene *sc, int enable)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    if (enable && sc->ev.empty()) {
+        sc->ev.resize(2 * kProfSlots);
+        sc->ev_kernel.resize(kProfSlots);
+        for (auto &e : sc->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    if (!enable && sc->prof) {
+        if (itm_status st = prof_flush(sc)) return st;
+    }
+    sc->prof = enable != 0;
+    return ITM_OK;
+}
+
+itm_status itm_profile_read(itm_scene *sc, double *ms, int64_t *launches)
+{
+    if (!sc || !ms || !launches) return fail(ITM_ERR_ARG, "NULL argument");
+    if (itm_status st = prof_flush(sc)) return st;
+    for (int k = 0; k < ITM_KERNEL_COUNT; k++) {
+        ms[k] = sc->prof_ms[k];
+        launches[k] = sc->prof_n[k];
+        sc->prof_ms[k] = 0;
+        sc->prof_n[k] = 0;
+    }
+    return ITM_OK;
+}
+
+}  // extern "C"
