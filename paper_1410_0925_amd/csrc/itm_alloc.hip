@@ -46,6 +46,9 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
         const unsigned long long old = atomicCAS(&B->key[i], 0ull, key);
         if (old == 0ull) {
             B->ptr[i] = atomicAdd(&a.cnt->vba_next, 1);
+            if (i == 0) atomicOr(&h.occ[b >> 5], 1u << (b & 31));  // slot 0 fills first
+            const uint32_t m = macro_index(bx, by, bz, h.macro_mask);
+            atomicOr(&h.macro[m >> 5], 1u << (m & 31));
             return 2 * (int32_t)b + i;
         }
         if (old == key) return 2 * (int32_t)b + i;
@@ -75,6 +78,10 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
     Excess *E = h.excess + x;
     E->key = key;
     E->ptr = atomicAdd(&a.cnt->vba_next, 1);
+    {
+        const uint32_t m = macro_index(bx, by, bz, h.macro_mask);
+        atomicOr(&h.macro[m >> 5], 1u << (m & 31));
+    }
     // link at the end of the chain; every failed compare-and-swap means another
     // claimant linked first, so the walk moves on and terminates
     int32_t *loc = &B->head;
@@ -249,7 +256,8 @@ __global__ void k_init_vba(typename Vox<FMT>::S *sdf, typename Vox<FMT>::Wt *w, 
 }
 
 __global__ void k_init_hash(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_t *vis, int64_t nvis,
-                            unsigned long long *set, int64_t nset, Counters *cnt)
+                            unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
+                            Counters *cnt)
 {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -266,6 +274,7 @@ __global__ void k_init_hash(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_
     }
     for (int64_t i = t0; i < nvis; i += stride) vis[i] = 0;
     for (int64_t i = t0; i < nset; i += stride) set[i] = 0ull;
+    for (int64_t i = t0; i < nocc; i += stride) occ[i] = 0u;
     if (t0 == 0) {
         Counters z = {};
         *cnt = z;
@@ -273,10 +282,10 @@ __global__ void k_init_hash(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_
 }
 
 hipError_t launch_init(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_t *vis, int64_t nvis,
-                       unsigned long long *set, int64_t nset, Counters *cnt, int fmt, void *sdf,
-                       void *w, int64_t n_vox, hipStream_t st)
+                       unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
+                       Counters *cnt, int fmt, void *sdf, void *w, int64_t n_vox, hipStream_t st)
 {
-    k_init_hash<<<2048, 256, 0, st>>>(b, nb, x, nx, vis, nvis, set, nset, cnt);
+    k_init_hash<<<2048, 256, 0, st>>>(b, nb, x, nx, vis, nvis, set, nset, occ, nocc, cnt);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     switch (fmt) {

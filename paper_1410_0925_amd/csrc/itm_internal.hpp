@@ -64,6 +64,10 @@ struct Counters {
 struct HashView {
     Bucket *buckets;
     Excess *excess;
+    uint32_t *occ;      // one bit per bucket: set once the bucket holds a block
+    uint32_t *macro;    // one bit per hashed macro cell (4^3 blocks): set once any
+                        // block of a cell hashing there is allocated
+    uint32_t macro_mask;
     uint32_t mask;
     int32_t n_buckets;
     int32_t n_excess;
@@ -101,7 +105,10 @@ __device__ __forceinline__ int32_t find_block(const HashView &h, int x, int y, i
 {
     if (!in_key_range(x, y, z)) return -1;
     const unsigned long long key = pack_key(x, y, z);
-    const Bucket *B = h.buckets + hash_index(x, y, z, h.mask);
+    const uint32_t b = hash_index(x, y, z, h.mask);
+    // an empty bucket holds no block (the bitmap is small enough to stay in L2)
+    if (!((h.occ[b >> 5] >> (b & 31)) & 1u)) return -1;
+    const Bucket *B = h.buckets + b;
     const ulonglong2 keys = *reinterpret_cast<const ulonglong2 *>(B->key);
     const int4 rest = *reinterpret_cast<const int4 *>(&B->ptr[0]);  // ptr0, ptr1, head, pad
     if (keys.x == key) return rest.x;
@@ -222,7 +229,19 @@ hipError_t launch_compact(const CompactArgs &a, int grid, hipStream_t st);
 hipError_t launch_integrate(int fmt, const IntegrateArgs &a, int grid, hipStream_t st);
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st);
 hipError_t launch_init(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_t *vis, int64_t nvis,
-                       unsigned long long *set, int64_t nset, Counters *cnt, int fmt, void *sdf,
-                       void *w, int64_t n_vox, hipStream_t st);
+                       unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
+                       Counters *cnt, int fmt, void *sdf, void *w, int64_t n_vox, hipStream_t st);
+
+constexpr int kMacroShift = 2;   // macro cell = 4 x 4 x 4 blocks
+
+__device__ __forceinline__ uint32_t macro_index(int bx, int by, int bz, uint32_t mask)
+{
+    return hash_index(bx >> kMacroShift, by >> kMacroShift, bz >> kMacroShift, mask);
+}
+__device__ __forceinline__ bool macro_set(const HashView &h, int bx, int by, int bz)
+{
+    const uint32_t m = macro_index(bx, by, bz, h.macro_mask);
+    return (h.macro[m >> 5] >> (m & 31)) & 1u;
+}
 
 }  // namespace itm

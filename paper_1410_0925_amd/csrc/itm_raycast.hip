@@ -13,7 +13,9 @@
 // t += F_t mu once behind the surface); the normal is the normalised central
 // difference of F_t at +-1 voxel along the world axes.
 // A one-entry register cache of the last block looked up saves most hash probes:
-// consecutive samples of a ray mostly fall in the same block.
+// consecutive samples of a ray mostly fall in the same block.  Coarse samples in
+// space with no allocated block are skipped a macro cell (4^3 blocks) at a time
+// through a hashed occupancy bitmap; the samples taken keep the 8 s spacing.
 #include "itm_internal.hpp"
 
 namespace itm {
@@ -38,42 +40,81 @@ struct BlockReader {
         }
         return cptr;
     }
-    // F at lattice voxel (vx, vy, vz); returns false (F = 1) when unallocated
-    __device__ bool voxel(int vx, int vy, int vz, float &F)
+    // F at the nearest lattice voxel of q; false (F = 1) when its block is absent
+    __device__ bool nearest(float qx, float qy, float qz, float &F)
     {
+        const int vx = (int)floorf(qx + 0.5f), vy = (int)floorf(qy + 0.5f), vz = (int)floorf(qz + 0.5f);
         const int32_t p = block(vx >> 3, vy >> 3, vz >> 3);
         if (p < 0) { F = 1.0f; return false; }
         F = Vox<FMT>::to_f(sdf[(int64_t)p * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7)]);
         return true;
     }
-    __device__ bool nearest(float qx, float qy, float qz, float &F)
+};
+
+// The blocks covering a lattice region of at most 9 voxels per axis (so at most
+// 2 x 2 x 2 blocks), looked up together so that their hash probes overlap; then
+// any voxel of the region is read with one gather.
+template <int FMT>
+struct Cube {
+    int bx0, by0, bz0;
+    int32_t p[8];   // block pointer of (dx, dy, dz) = (c & 1, c >> 1 & 1, c >> 2 & 1)
+
+    __device__ void fetch(const HashView &h, int lx, int ly, int lz, int hx, int hy, int hz)
     {
-        return voxel((int)floorf(qx + 0.5f), (int)floorf(qy + 0.5f), (int)floorf(qz + 0.5f), F);
+        bx0 = lx >> 3; by0 = ly >> 3; bz0 = lz >> 3;
+        const int bx1 = hx >> 3, by1 = hy >> 3, bz1 = hz >> 3;
+        const bool sx = bx1 != bx0, sy = by1 != by0, sz = bz1 != bz0;
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+            const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
+            p[c] = need ? find_block(h, dx ? bx1 : bx0, dy ? by1 : by0, dz ? bz1 : bz0) : -1;
+        }
     }
-    __device__ float trilinear(float qx, float qy, float qz)
+    __device__ float F(const typename Vox<FMT>::S *sdf, int vx, int vy, int vz) const
     {
-        const float flx = floorf(qx), fly = floorf(qy), flz = floorf(qz);
-        const int ix = (int)flx, iy = (int)fly, iz = (int)flz;
-        const float rx = qx - flx, ry = qy - fly, rz = qz - flz;
+        const bool ex = (vx >> 3) != bx0, ey = (vy >> 3) != by0, ez = (vz >> 3) != bz0;
+        const int32_t a0 = ex ? p[1] : p[0], a1 = ex ? p[3] : p[2];
+        const int32_t a2 = ex ? p[5] : p[4], a3 = ex ? p[7] : p[6];
+        const int32_t b0 = ey ? a1 : a0, b1 = ey ? a3 : a2;
+        const int32_t ptr = ez ? b1 : b0;
+        if (ptr < 0) return 1.0f;
+        return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7)]);
+    }
+    // trilinear interpolation at q with i = floor(q) inside the region
+    __device__ float trilinear(const typename Vox<FMT>::S *sdf, int ix, int iy, int iz, float rx,
+                               float ry, float rz) const
+    {
         float acc = 0.0f;
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
-            float F;
-            voxel(ix + dx, iy + dy, iz + dz, F);
             const float w = (dx ? rx : 1.0f - rx) * (dy ? ry : 1.0f - ry) * (dz ? rz : 1.0f - rz);
-            acc = fmaf(w, F, acc);
+            acc = fmaf(w, F(sdf, ix + dx, iy + dy, iz + dz), acc);
         }
         return acc;
     }
 };
 
 template <int FMT>
+__device__ float trilinear_at(const HashView &h, const typename Vox<FMT>::S *sdf, float qx, float qy,
+                              float qz)
+{
+    const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    Cube<FMT> cb;
+    cb.fetch(h, ix, iy, iz, ix + 1, iy + 1, iz + 1);
+    return cb.trilinear(sdf, ix, iy, iz, qx - fx, qy - fy, qz - fz);
+}
+
+template <int FMT>
 __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
 {
     const FrameGeom &g = a.fg;
-    const int u = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int v = blockIdx.y * 16 + (threadIdx.x >> 4);
+    // a workgroup covers 16 x 16 pixels, each wave an 8 x 8 quadrant of it
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int u = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
+    const int v = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
     if (u >= g.W || v >= g.H) return;
     const int64_t pix = (int64_t)v * g.W + u;
 
@@ -89,18 +130,45 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     const float s = g.s_f, mu = g.mu_f, bs = 8.0f * g.s_f;
     const int fine_budget = (int)ceilf(bs / mu) + 1;
     const int cap = (int)((t_far - t_near) / s) * 4 + 1000;
+    // reciprocal direction for the macro-cell exit
+    const float idx = 1.0f / dx, idy = 1.0f / dy, idz = 1.0f / dz;
 
     BlockReader<FMT> rd(a.h, a.sdf);
     float t = t_near;
     int state = RC_COARSE, fine_miss = 0;
     for (int it = 0; it < cap && t < t_far; it++) {
         const float qx = fmaf(t, dx, ox), qy = fmaf(t, dy, oy), qz = fmaf(t, dz, oz);
+        if (state == RC_COARSE) {
+            const int vx = (int)floorf(qx + 0.5f), vy = (int)floorf(qy + 0.5f), vz = (int)floorf(qz + 0.5f);
+            const int bx = vx >> 3, by = vy >> 3, bz = vz >> 3;
+            if (!macro_set(a.h, bx, by, bz)) {
+                // Every sample whose nearest voxel lies in this empty macro cell is a
+                // miss: jump over them, keeping the sample spacing of 8 s.  The cell
+                // in sample space is [32 m - 1/2, 32 (m + 1) - 1/2) per axis, shrunk
+                // by 1e-3 voxel against rounding.
+                const float e = 1e-3f;
+                const float lx = (float)((bx >> kMacroShift) * 32) - 0.5f;
+                const float ly = (float)((by >> kMacroShift) * 32) - 0.5f;
+                const float lz = (float)((bz >> kMacroShift) * 32) - 0.5f;
+                const float tx = dx > 0.0f ? (lx + 32.0f - e - ox) * idx
+                                 : dx < 0.0f ? (lx + e - ox) * idx : INFINITY;
+                const float ty = dy > 0.0f ? (ly + 32.0f - e - oy) * idy
+                                 : dy < 0.0f ? (ly + e - oy) * idy : INFINITY;
+                const float tz = dz > 0.0f ? (lz + 32.0f - e - oz) * idz
+                                 : dz < 0.0f ? (lz + e - oz) * idz : INFINITY;
+                const float t_exit = fminf(tx, fminf(ty, tz));
+                const float m = fmaxf(ceilf((t_exit - t) / bs), 1.0f);
+                t = fmaf(m, bs, t);
+                continue;
+            }
+            float F;
+            if (!rd.nearest(qx, qy, qz, F)) t += bs;
+            else { t = fmaxf(t - bs, t_near); state = RC_FINE; fine_miss = 0; }
+            continue;
+        }
         float F;
         const bool found = rd.nearest(qx, qy, qz, F);
-        if (state == RC_COARSE) {
-            if (!found) t += bs;
-            else { t = fmaxf(t - bs, t_near); state = RC_FINE; fine_miss = 0; }
-        } else if (state == RC_FINE) {
+        if (state == RC_FINE) {
             if (!found) {
                 t += mu;
                 if (++fine_miss > fine_budget) state = RC_COARSE;
@@ -117,15 +185,22 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     }
     float4 P = make_float4(0.f, 0.f, 0.f, 0.f), N = make_float4(0.f, 0.f, 0.f, 0.f);
     if (state == RC_BEHIND) {
+        const auto *sdf = (const typename Vox<FMT>::S *)a.sdf;
 #pragma unroll
         for (int k = 0; k < 2; k++)
-            t = fmaf(rd.trilinear(fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz)), mu, t);
+            t = fmaf(trilinear_at<FMT>(a.h, sdf, fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz)), mu, t);
         const float qx = fmaf(t, dx, ox), qy = fmaf(t, dy, oy), qz = fmaf(t, dz, oz);
         P = make_float4((float)(g.twc[0] + (double)t * dir[0]), (float)(g.twc[1] + (double)t * dir[1]),
                         (float)(g.twc[2] + (double)t * dir[2]), 1.0f);
-        const float gx = rd.trilinear(qx + 1.0f, qy, qz) - rd.trilinear(qx - 1.0f, qy, qz);
-        const float gy = rd.trilinear(qx, qy + 1.0f, qz) - rd.trilinear(qx, qy - 1.0f, qz);
-        const float gz = rd.trilinear(qx, qy, qz + 1.0f) - rd.trilinear(qx, qy, qz - 1.0f);
+        // the six samples q +- e_a read voxels floor(q) - 1 .. floor(q) + 2
+        const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+        const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+        const float rx = qx - fx, ry = qy - fy, rz = qz - fz;
+        Cube<FMT> cb;
+        cb.fetch(a.h, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
+        const float gx = cb.trilinear(sdf, ix + 1, iy, iz, rx, ry, rz) - cb.trilinear(sdf, ix - 1, iy, iz, rx, ry, rz);
+        const float gy = cb.trilinear(sdf, ix, iy + 1, iz, rx, ry, rz) - cb.trilinear(sdf, ix, iy - 1, iz, rx, ry, rz);
+        const float gz = cb.trilinear(sdf, ix, iy, iz + 1, rx, ry, rz) - cb.trilinear(sdf, ix, iy, iz - 1, rx, ry, rz);
         const float n2 = gx * gx + gy * gy + gz * gz;
         if (n2 > 0.0f) {
             const float r = 1.0f / sqrtf(n2);

@@ -46,6 +46,9 @@ int64_t next_pow2(int64_t x)
 
 constexpr int kProfSlots = 4096;
 
+// macro-cell bitmap: a power of two of bits, half the bucket count, at least 2^16
+int64_t macro_words(int64_t n_buckets) { return std::max<int64_t>(n_buckets / 2, 1 << 16) / 32; }
+
 }  // namespace
 
 struct itm_scene {
@@ -68,6 +71,9 @@ struct itm_scene {
     unsigned long long *set = nullptr;
     int32_t *set_list = nullptr;
     Counters *cnt = nullptr;
+    uint32_t *occ = nullptr;
+    int64_t occ_words = 0;
+    int64_t macro_bits = 0;
     int32_t *hint_host = nullptr;  // mapped pinned word written by k_compact
     int32_t *hint_dev = nullptr;
 
@@ -98,6 +104,7 @@ void release(itm_scene *sc)
     (void)hipFree(sc->set);
     (void)hipFree(sc->set_list);
     (void)hipFree(sc->cnt);
+    (void)hipFree(sc->occ);
     if (sc->hint_host) (void)hipHostFree(sc->hint_host);
     delete sc;
 }
@@ -162,6 +169,9 @@ HashView hash_view(const itm_scene *sc)
     HashView h;
     h.buckets = sc->buckets;
     h.excess = sc->excess;
+    h.occ = sc->occ;
+    h.macro = sc->occ + sc->occ_words;
+    h.macro_mask = (uint32_t)(sc->macro_bits - 1);
     h.mask = sc->mask;
     h.n_buckets = (int32_t)sc->n_buckets;
     h.n_excess = (int32_t)sc->n_excess;
@@ -277,7 +287,9 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
         dev_alloc(&sc->w, w_elem(fmt) * n_vox, "weights") ||
         dev_alloc((void **)&sc->set, sizeof(unsigned long long) * sc->set_size, "claim set") ||
         dev_alloc((void **)&sc->set_list, sizeof(int32_t) * sc->set_size, "claim list") ||
-        dev_alloc((void **)&sc->cnt, sizeof(Counters), "counters")) {
+        dev_alloc((void **)&sc->cnt, sizeof(Counters), "counters") ||
+        dev_alloc((void **)&sc->occ, sizeof(uint32_t) * ((n_buckets + 31) / 32 + macro_words(n_buckets)),
+                  "occupancy bitmaps")) {
         release(sc);
         return nullptr;
     }
@@ -289,8 +301,11 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
     } else {
         *sc->hint_host = 0;
     }
+    sc->occ_words = (n_buckets + 31) / 32;
+    sc->macro_bits = macro_words(n_buckets) * 32;
     hipError_t e = launch_init(sc->buckets, n_buckets, sc->excess, n_excess, sc->vis, sc->vis_bytes,
-                               sc->set, sc->set_size, sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
+                               sc->set, sc->set_size, sc->occ, sc->occ_words + macro_words(n_buckets),
+                               sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     if (e != hipSuccess) {
         fail(ITM_ERR_HIP, "scene initialisation failed: %s", hipGetErrorString(e));
