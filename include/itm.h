@@ -151,6 +151,53 @@ itm_status itm_profile_enable(itm_scene *scene, int enable);
  * id since profiling was enabled, and resets them. */
 itm_status itm_profile_read(itm_scene *scene, double *ms, int64_t *launches);
 
+/* ------------------------------------------------------------------------ */
+/* Learned block refiner.  Not part of the paper's method: a small 3D           */
+/* convolutional network, trained on pairs the method itself produces, maps a   */
+/* block's few-frame TSDF (with a one-voxel halo) towards the TSDF the running  */
+/* average reaches after many frames.  Layers (each a 3^3 convolution from the  */
+/* 10^3 haloed / zero-padded grid to the 8^3 block): 2->16 ReLU, 16->16 ReLU,    */
+/* 16->16 ReLU, 16->1; F_out = clamp(F + L4, -1, 1).  bf16 operands on MFMA,     */
+/* float32 accumulation, float32 master weights.                                */
+/* Parameter vector: for layers 1..4 W[tap][co][ci] (tap = dz*9 + dy*3 + dx,     */
+/* co, ci in 0..15, unused channels 0), then the biases b[layer][co].            */
+/* Network input of a block: float32 [2][10][10][10] = (F, W / max_w) on the     */
+/* voxels 8 k - 1 .. 8 k + 8 per axis; voxels of absent blocks read (1, 0).       */
+/* ------------------------------------------------------------------------ */
+#define ITM_REFINE_PARAMS 27712
+typedef struct itm_refiner itm_refiner; /* opaque, owned by the library */
+
+/* params: HOST float[ITM_REFINE_PARAMS] (copied).  NULL on failure. */
+itm_refiner *itm_refiner_create(const float *params, void *hip_stream);
+void itm_refiner_destroy(itm_refiner *refiner);
+itm_status itm_refiner_set_stream(itm_refiner *refiner, void *hip_stream);
+/* params: HOST float[ITM_REFINE_PARAMS] out (synchronises). */
+itm_status itm_refiner_get_params(itm_refiner *refiner, float *params);
+/* in: DEVICE float[n][2][1000]; out: DEVICE float[n][512] refined F.  Async. */
+itm_status itm_refiner_forward(itm_refiner *refiner, const float *in, int64_t n, float *out);
+/* Mean squared error of F_out against target over the voxels with mask != 0,
+ * summed over the n blocks and divided by the count of such voxels, and its
+ * gradient.  in: DEVICE float[n][2][1000]; target: DEVICE float[n][512]; mask:
+ * DEVICE uint8[n][512]; grad: DEVICE float[ITM_REFINE_PARAMS] or NULL; loss:
+ * DEVICE float[1] or NULL.  Async; scratch grows with n (about 111 KB per block). */
+itm_status itm_refiner_gradient(itm_refiner *refiner, const float *in, const float *target,
+                                const uint8_t *mask, int64_t n, float *grad, float *loss);
+/* The gradient above, then one Adam step (beta 0.9, 0.999, eps 1e-8) on the
+ * float32 master weights and a re-rounding of the bf16 copies.  Async. */
+itm_status itm_refiner_train_step(itm_refiner *refiner, const float *in, const float *target,
+                                  const uint8_t *mask, int64_t n, float lr, float *loss);
+/* Network inputs of the blocks at coords (DEVICE int32[n][3]) from the scene's
+ * volume into out (DEVICE float[n][2][1000]).  Async. */
+itm_status itm_gather_blocks(itm_scene *scene, const int32_t *coords, int64_t n, float *out);
+/* Attach a refiner (not owned; NULL detaches): after every integration each
+ * visible block whose largest weight is below w_threshold is refined into a side
+ * buffer (half precision, one per voxel block; allocated on first attach). */
+itm_status itm_scene_set_refiner(itm_scene *scene, itm_refiner *refiner, float w_threshold);
+/* As itm_export_blocks for F, with the refined F of the blocks refined in the
+ * last integration; refined: HOST uint8[capacity] or NULL, 1 where refined. */
+itm_status itm_export_blocks_refined(itm_scene *scene, int32_t *coords, float *sdf, uint8_t *refined,
+                                     int64_t capacity, int64_t *n_blocks);
+
 /* Reason of the last failing call on this thread ("" if none). */
 const char *itm_last_error(void);
 

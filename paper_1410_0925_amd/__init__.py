@@ -45,7 +45,12 @@ _lib = None
 _P = C.c_void_p
 EXPORTED = ("itm_scene_create", "itm_scene_create_ex", "itm_scene_destroy", "itm_set_stream",
             "itm_integrate", "itm_raycast", "itm_export_blocks", "itm_get_stats",
-            "itm_profile_enable", "itm_profile_read", "itm_last_error")
+            "itm_profile_enable", "itm_profile_read", "itm_last_error",
+            "itm_refiner_create", "itm_refiner_destroy", "itm_refiner_set_stream",
+            "itm_refiner_get_params", "itm_refiner_forward", "itm_refiner_gradient",
+            "itm_refiner_train_step", "itm_gather_blocks", "itm_scene_set_refiner",
+            "itm_export_blocks_refined")
+ITM_REFINE_PARAMS = 27712
 
 
 def lib():
@@ -69,6 +74,16 @@ def lib():
             "itm_profile_enable": (C.c_int, [_P, C.c_int]),
             "itm_profile_read": (C.c_int, [_P, _P, _P]),
             "itm_last_error": (C.c_char_p, []),
+            "itm_refiner_create": (_P, [_P, _P]),
+            "itm_refiner_destroy": (None, [_P]),
+            "itm_refiner_set_stream": (C.c_int, [_P, _P]),
+            "itm_refiner_get_params": (C.c_int, [_P, _P]),
+            "itm_refiner_forward": (C.c_int, [_P, _P, C.c_int64, _P]),
+            "itm_refiner_gradient": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, _P]),
+            "itm_refiner_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, _P]),
+            "itm_gather_blocks": (C.c_int, [_P, _P, C.c_int64, _P]),
+            "itm_scene_set_refiner": (C.c_int, [_P, _P, C.c_float]),
+            "itm_export_blocks_refined": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -188,6 +203,112 @@ def itm_last_error():
     return lib().itm_last_error().decode()
 
 
+def itm_refiner_create(params, stream=None):
+    p = np.ascontiguousarray(params, np.float32)
+    if p.size != ITM_REFINE_PARAMS:
+        raise ValueError(f"expected {ITM_REFINE_PARAMS} parameters")
+    h = lib().itm_refiner_create(p.ctypes.data_as(_P), stream)
+    if not h:
+        raise ItmError(ITM_ERR_ARG, lib().itm_last_error().decode())
+    return h
+
+
+def itm_refiner_destroy(h):
+    lib().itm_refiner_destroy(h)
+
+
+def itm_refiner_get_params(h):
+    out = np.empty(ITM_REFINE_PARAMS, np.float32)
+    _check(lib().itm_refiner_get_params(h, out.ctypes.data_as(_P)))
+    return out
+
+
+def itm_refiner_forward(h, inputs, out):
+    n = inputs.shape[0]
+    _check(lib().itm_refiner_forward(h, _dev(inputs, "torch.float32", n * 2000), n,
+                                     _dev(out, "torch.float32", n * 512)))
+
+
+def itm_refiner_gradient(h, inputs, target, mask, grad=None, loss=None):
+    n = inputs.shape[0]
+    _check(lib().itm_refiner_gradient(
+        h, _dev(inputs, "torch.float32", n * 2000), _dev(target, "torch.float32", n * 512),
+        _dev(mask, "torch.uint8", n * 512), n,
+        None if grad is None else _dev(grad, "torch.float32", ITM_REFINE_PARAMS),
+        None if loss is None else _dev(loss, "torch.float32", 1)))
+
+
+def itm_refiner_train_step(h, inputs, target, mask, lr, loss=None):
+    n = inputs.shape[0]
+    _check(lib().itm_refiner_train_step(
+        h, _dev(inputs, "torch.float32", n * 2000), _dev(target, "torch.float32", n * 512),
+        _dev(mask, "torch.uint8", n * 512), n, float(lr),
+        None if loss is None else _dev(loss, "torch.float32", 1)))
+
+
+def itm_gather_blocks(h, coords, out):
+    n = coords.shape[0]
+    _check(lib().itm_gather_blocks(h, _dev(coords, "torch.int32", n * 3), n,
+                                   _dev(out, "torch.float32", n * 2000)))
+
+
+def itm_scene_set_refiner(h, refiner, w_threshold):
+    _check(lib().itm_scene_set_refiner(h, refiner, float(w_threshold)))
+
+
+def itm_export_blocks_refined(h):
+    n = C.c_int64(0)
+    _check(lib().itm_export_blocks_refined(h, None, None, None, 0, C.byref(n)))
+    m = n.value
+    coords = np.empty((m, 3), np.int32)
+    sdf = np.empty((m, 512), np.float32)
+    flags = np.empty(m, np.uint8)
+    _check(lib().itm_export_blocks_refined(h, coords.ctypes.data_as(_P), sdf.ctypes.data_as(_P),
+                                           flags.ctypes.data_as(_P), m, C.byref(n)))
+    return coords, sdf, flags.astype(bool)
+
+
+class Refiner:
+    """The learned block refiner on the current GPU (owns the library object)."""
+
+    def __init__(self, params):
+        self.h = itm_refiner_create(params, _stream())
+
+    def close(self):
+        if getattr(self, "h", None):
+            itm_refiner_destroy(self.h)
+            self.h = None
+
+    __del__ = close
+
+    def _sync_stream(self):
+        _check(lib().itm_refiner_set_stream(self.h, _stream()))
+
+    def params(self):
+        self._sync_stream()
+        return itm_refiner_get_params(self.h)
+
+    def forward(self, inputs, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((inputs.shape[0], 512), dtype=torch.float32, device="cuda")
+        self._sync_stream()
+        itm_refiner_forward(self.h, inputs, out)
+        return out
+
+    def gradient(self, inputs, target, mask):
+        import torch
+        g = torch.empty(ITM_REFINE_PARAMS, dtype=torch.float32, device="cuda")
+        l = torch.empty(1, dtype=torch.float32, device="cuda")
+        self._sync_stream()
+        itm_refiner_gradient(self.h, inputs, target, mask, g, l)
+        return g, l
+
+    def train_step(self, inputs, target, mask, lr, loss=None):
+        self._sync_stream()
+        itm_refiner_train_step(self.h, inputs, target, mask, lr, loss)
+
+
 # ---------------------------------------------------------------------------
 # convenience wrapper
 # ---------------------------------------------------------------------------
@@ -243,6 +364,24 @@ class Scene:
     def stats(self):
         self._sync_stream()
         return itm_get_stats(self.h)
+
+    def gather(self, coords):
+        """Network inputs [n, 2, 1000] of the blocks at coords (int32 [n, 3])."""
+        import torch
+        c = torch.as_tensor(np.ascontiguousarray(coords, np.int32)).cuda()
+        out = torch.empty((c.shape[0], 2000), dtype=torch.float32, device="cuda")
+        self._sync_stream()
+        itm_gather_blocks(self.h, c, out)
+        return out
+
+    def set_refiner(self, refiner, w_threshold=10.0):
+        self._sync_stream()
+        itm_scene_set_refiner(self.h, None if refiner is None else refiner.h, w_threshold)
+        self._refiner = refiner   # keep it alive while attached
+
+    def export_refined(self):
+        self._sync_stream()
+        return itm_export_blocks_refined(self.h)
 
     def profile(self, enable=True):
         itm_profile_enable(self.h, enable)

@@ -47,7 +47,7 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
         if (old == 0ull) {
             B->ptr[i] = atomicAdd(&a.cnt->vba_next, 1);
             if (i == 0) atomicOr(&h.occ[b >> 5], 1u << (b & 31));  // slot 0 fills first
-            const uint32_t m = macro_index(bx, by, bz, h.macro_mask);
+            const uint32_t m = macro_index(bx, by, bz);
             atomicOr(&h.macro[m >> 5], 1u << (m & 31));
             return 2 * (int32_t)b + i;
         }
@@ -79,7 +79,7 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
     E->key = key;
     E->ptr = atomicAdd(&a.cnt->vba_next, 1);
     {
-        const uint32_t m = macro_index(bx, by, bz, h.macro_mask);
+        const uint32_t m = macro_index(bx, by, bz);
         atomicOr(&h.macro[m >> 5], 1u << (m & 31));
     }
     // link at the end of the chain; every failed compare-and-swap means another
@@ -96,12 +96,14 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
 __global__ __launch_bounds__(256) void k_alloc(AllocArgs a)
 {
     const FrameGeom &g = a.fg;
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (blockIdx.x == 0) {
         if (threadIdx.x == 0) a.cnt->n_vis = 0;                 // filled by k_compact
         if (threadIdx.x < kStripes) a.cnt->upd[0][threadIdx.x][0] = 0;  // filled by k_integrate
     }
-    const int u = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int v = blockIdx.y * 16 + (threadIdx.x >> 4);
+    int tx, ty;
+    if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;
+    const int u = tx * 16 + (threadIdx.x & 15);
+    const int v = ty * 16 + (threadIdx.x >> 4);
     if (u >= g.W || v >= g.H) return;
     const float depth = a.depth[(int64_t)v * g.W + u];
     if (!(depth > 0.0f) || isinf(depth)) return;
@@ -161,8 +163,7 @@ __global__ __launch_bounds__(256) void k_alloc(AllocArgs a)
 
 hipError_t launch_alloc(const AllocArgs &a, hipStream_t st)
 {
-    dim3 grid((a.fg.W + 15) / 16, (a.fg.H + 15) / 16);
-    k_alloc<<<grid, 256, 0, st>>>(a);
+    k_alloc<<<xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16)), 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

@@ -65,9 +65,8 @@ struct HashView {
     Bucket *buckets;
     Excess *excess;
     uint32_t *occ;      // one bit per bucket: set once the bucket holds a block
-    uint32_t *macro;    // one bit per hashed macro cell (4^3 blocks): set once any
-                        // block of a cell hashing there is allocated
-    uint32_t macro_mask;
+    uint32_t *macro;    // kMacroBits bits, one per hashed macro cell (4^3 blocks): set
+                        // once any block of a cell hashing there is allocated
     uint32_t mask;
     int32_t n_buckets;
     int32_t n_excess;
@@ -223,6 +222,51 @@ struct RaycastArgs {
     float4 *nrm;
 };
 
+// learned refiner (itm_refine.hip)
+constexpr int kRefineWeights = 4 * 27 * 16 * 16;       // [layer][tap][co][ci]
+constexpr int kRefineParams = kRefineWeights + 4 * 16;  // + biases [layer][co]
+
+struct RefineParams {
+    const uint16_t *Wf;   // bf16 [l][tap][co][ci]   (forward operand)
+    const uint16_t *Wt;   // bf16 [l][tap][ci][co]   (data-gradient operand)
+    const float *bias;    // float32 [l][co]
+};
+
+struct RefineArgs {
+    RefineParams P;
+    const float *in;        // [n][2][1000]
+    int64_t n;
+    float *out;             // [n][512] refined F, or null
+    const float *target;    // [n][512]  (training)
+    const uint8_t *mask;    // [n][512]  (training)
+    float *grad_part;       // [n][kRefineParams]  (training)
+    float *loss_part;       // [n][2]: sum of squared errors, count (training)
+};
+
+struct RefineGateArgs {
+    RefineParams P;
+    HashView h;
+    const int32_t *vis_list;
+    const Counters *cnt;
+    const void *sdf;
+    const void *w;
+    float inv_max_w;
+    float w_threshold;
+    __half *refined;      // [capacity][512]
+    int32_t *stamp;       // [capacity]: frame of the last refinement
+    int32_t frame;
+};
+
+hipError_t launch_refine(const RefineArgs &a, bool train, int grid, hipStream_t st);
+hipError_t launch_refine_gated(int fmt, const RefineGateArgs &a, int grid, hipStream_t st);
+hipError_t launch_refine_reduce(const float *grad_part, const float *loss_part, int64_t n, float *grad,
+                                float *loss, hipStream_t st);
+hipError_t launch_refine_adam(float *master, float *m, float *v, const float *grad, uint16_t *Wf, uint16_t *Wt,
+                              float *bias, float lr, int step, hipStream_t st);
+hipError_t launch_refine_cast(const float *master, uint16_t *Wf, uint16_t *Wt, float *bias, hipStream_t st);
+hipError_t launch_refine_gather(int fmt, const HashView &h, const void *sdf, const void *w, const int32_t *coords,
+                                int64_t n, float inv_max_w, float *out, hipStream_t st);
+
 // launchers (one translation unit each)
 hipError_t launch_alloc(const AllocArgs &a, hipStream_t st);
 hipError_t launch_compact(const CompactArgs &a, int grid, hipStream_t st);
@@ -232,16 +276,50 @@ hipError_t launch_init(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_t *vi
                        unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
                        Counters *cnt, int fmt, void *sdf, void *w, int64_t n_vox, hipStream_t st);
 
-constexpr int kMacroShift = 2;   // macro cell = 4 x 4 x 4 blocks
-
-__device__ __forceinline__ uint32_t macro_index(int bx, int by, int bz, uint32_t mask)
+// Workgroups are handed to the 8 XCDs round-robin by id.  Image tiles are
+// renumbered so that XCD k gets a contiguous band of tiles: rays and pixels of a
+// band touch the same hash buckets and voxel blocks, which then stay in that XCD's
+// L2.  Returns false for the padding ids past the last tile.
+constexpr int kXcds = 8;
+__device__ __forceinline__ bool xcd_tile(int n_tx, int n_ty, int &tx, int &ty)
 {
-    return hash_index(bx >> kMacroShift, by >> kMacroShift, bz >> kMacroShift, mask);
+    const int n = n_tx * n_ty;
+    const int per = (n + kXcds - 1) / kXcds;
+    const int b = blockIdx.x;
+    const int tile = (b % kXcds) * per + b / kXcds;
+    if (tile >= n) return false;
+    tx = tile % n_tx;
+    ty = tile / n_tx;
+    return true;
 }
-__device__ __forceinline__ bool macro_set(const HashView &h, int bx, int by, int bz)
+__host__ __forceinline__ int xcd_grid(int n_tiles) { return (n_tiles + kXcds - 1) / kXcds * kXcds; }
+
+constexpr int kMacroShift = 2;         // macro cell = 4 x 4 x 4 blocks
+constexpr int kMacroBits = 1 << 17;    // 16 KiB: small enough to sit in LDS
+constexpr int kMacroWords = kMacroBits / 32;
+
+__device__ __forceinline__ uint32_t macro_index(int bx, int by, int bz)
 {
-    const uint32_t m = macro_index(bx, by, bz, h.macro_mask);
-    return (h.macro[m >> 5] >> (m & 31)) & 1u;
+    return hash_index(bx >> kMacroShift, by >> kMacroShift, bz >> kMacroShift, kMacroBits - 1);
+}
+
+// retrieval without the bucket bitmap, for blocks that are probably allocated
+__device__ __forceinline__ int32_t find_block_direct(const HashView &h, int x, int y, int z)
+{
+    if (!in_key_range(x, y, z)) return -1;
+    const unsigned long long key = pack_key(x, y, z);
+    const Bucket *B = h.buckets + hash_index(x, y, z, h.mask);
+    const ulonglong2 keys = *reinterpret_cast<const ulonglong2 *>(B->key);
+    const int4 rest = *reinterpret_cast<const int4 *>(&B->ptr[0]);
+    if (keys.x == key) return rest.x;
+    if (keys.y == key) return rest.y;
+    int32_t x_i = rest.z;
+    while (x_i >= 0) {
+        const Excess E = h.excess[x_i];
+        if (E.key == key) return E.ptr;
+        x_i = E.next;
+    }
+    return -1;
 }
 
 }  // namespace itm

@@ -59,7 +59,10 @@ struct Cube {
     int bx0, by0, bz0;
     int32_t p[8];   // block pointer of (dx, dy, dz) = (c & 1, c >> 1 & 1, c >> 2 & 1)
 
-    __device__ void fetch(const HashView &h, int lx, int ly, int lz, int hx, int hy, int hz)
+    // blocks near a surface are almost always allocated, so they are probed
+    // directly; the march's cached block is reused without a probe
+    __device__ void fetch(const HashView &h, const BlockReader<FMT> &rd, int lx, int ly, int lz, int hx,
+                          int hy, int hz)
     {
         bx0 = lx >> 3; by0 = ly >> 3; bz0 = lz >> 3;
         const int bx1 = hx >> 3, by1 = hy >> 3, bz1 = hz >> 3;
@@ -68,7 +71,9 @@ struct Cube {
         for (int c = 0; c < 8; c++) {
             const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
             const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
-            p[c] = need ? find_block(h, dx ? bx1 : bx0, dy ? by1 : by0, dz ? bz1 : bz0) : -1;
+            const int kx = dx ? bx1 : bx0, ky = dy ? by1 : by0, kz = dz ? bz1 : bz0;
+            const bool cached = kx == rd.cx && ky == rd.cy && kz == rd.cz;
+            p[c] = !need ? -1 : cached ? rd.cptr : find_block_direct(h, kx, ky, kz);
         }
     }
     __device__ float F(const typename Vox<FMT>::S *sdf, int vx, int vy, int vz) const
@@ -97,13 +102,13 @@ struct Cube {
 };
 
 template <int FMT>
-__device__ float trilinear_at(const HashView &h, const typename Vox<FMT>::S *sdf, float qx, float qy,
-                              float qz)
+__device__ float trilinear_at(const HashView &h, const BlockReader<FMT> &rd,
+                              const typename Vox<FMT>::S *sdf, float qx, float qy, float qz)
 {
     const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
     const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
     Cube<FMT> cb;
-    cb.fetch(h, ix, iy, iz, ix + 1, iy + 1, iz + 1);
+    cb.fetch(h, rd, ix, iy, iz, ix + 1, iy + 1, iz + 1);
     return cb.trilinear(sdf, ix, iy, iz, qx - fx, qy - fy, qz - fz);
 }
 
@@ -111,10 +116,20 @@ template <int FMT>
 __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
 {
     const FrameGeom &g = a.fg;
+    int tx, ty;
+    if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;  // whole workgroup
+    // the macro-cell bitmap, staged in LDS: empty-space tests cost an LDS read
+    __shared__ uint32_t s_macro[kMacroWords];
+    {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.h.macro);
+        uint4 *dst = reinterpret_cast<uint4 *>(s_macro);
+        for (int i = threadIdx.x; i < kMacroWords / 4; i += blockDim.x) dst[i] = src[i];
+    }
+    __syncthreads();
     // a workgroup covers 16 x 16 pixels, each wave an 8 x 8 quadrant of it
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int u = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
-    const int v = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
+    const int u = tx * 16 + (wave & 1) * 8 + (lane & 7);
+    const int v = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
     if (u >= g.W || v >= g.H) return;
     const int64_t pix = (int64_t)v * g.W + u;
 
@@ -141,7 +156,8 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
         if (state == RC_COARSE) {
             const int vx = (int)floorf(qx + 0.5f), vy = (int)floorf(qy + 0.5f), vz = (int)floorf(qz + 0.5f);
             const int bx = vx >> 3, by = vy >> 3, bz = vz >> 3;
-            if (!macro_set(a.h, bx, by, bz)) {
+            const uint32_t mi = macro_index(bx, by, bz);
+            if (!((s_macro[mi >> 5] >> (mi & 31)) & 1u)) {
                 // Every sample whose nearest voxel lies in this empty macro cell is a
                 // miss: jump over them, keeping the sample spacing of 8 s.  The cell
                 // in sample space is [32 m - 1/2, 32 (m + 1) - 1/2) per axis, shrunk
@@ -188,7 +204,7 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
         const auto *sdf = (const typename Vox<FMT>::S *)a.sdf;
 #pragma unroll
         for (int k = 0; k < 2; k++)
-            t = fmaf(trilinear_at<FMT>(a.h, sdf, fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz)), mu, t);
+            t = fmaf(trilinear_at<FMT>(a.h, rd, sdf, fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz)), mu, t);
         const float qx = fmaf(t, dx, ox), qy = fmaf(t, dy, oy), qz = fmaf(t, dz, oz);
         P = make_float4((float)(g.twc[0] + (double)t * dir[0]), (float)(g.twc[1] + (double)t * dir[1]),
                         (float)(g.twc[2] + (double)t * dir[2]), 1.0f);
@@ -197,7 +213,7 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
         const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
         const float rx = qx - fx, ry = qy - fy, rz = qz - fz;
         Cube<FMT> cb;
-        cb.fetch(a.h, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
+        cb.fetch(a.h, rd, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
         const float gx = cb.trilinear(sdf, ix + 1, iy, iz, rx, ry, rz) - cb.trilinear(sdf, ix - 1, iy, iz, rx, ry, rz);
         const float gy = cb.trilinear(sdf, ix, iy + 1, iz, rx, ry, rz) - cb.trilinear(sdf, ix, iy - 1, iz, rx, ry, rz);
         const float gz = cb.trilinear(sdf, ix, iy, iz + 1, rx, ry, rz) - cb.trilinear(sdf, ix, iy, iz - 1, rx, ry, rz);
@@ -213,7 +229,7 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
 
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st)
 {
-    dim3 grid((a.fg.W + 15) / 16, (a.fg.H + 15) / 16);
+    const int grid = xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16));
     switch (fmt) {
     case ITM_VOX_F32: k_raycast<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
     case ITM_VOX_F16: k_raycast<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;

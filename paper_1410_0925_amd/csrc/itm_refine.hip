@@ -1,0 +1,465 @@
+// Learned block refiner: a 4-layer 3D convolutional network on bf16 MFMA.
+//
+// Every layer is the same operation: a 3^3 convolution from a 10^3 grid (the
+// block with a one-voxel halo, or the 8^3 block zero-padded) to the 8^3 block,
+// 16 input and 16 output channels (layer 1 uses 2 real input channels, layer 4
+// one real output channel; the others hold zeros).  As an implicit GEMM per
+// block: M = 512 voxels, N = 16 output channels, K = 27 taps x 16 channels, so one
+// tap is one K step of v_mfma_f32_16x16x16_bf16.  A workgroup of 4 waves takes a
+// block; wave w owns the voxel tiles 8w..8w+7.  Activations live in LDS as bf16
+// [voxel][channel]; weights are read from global memory (L1-resident) as bf16.
+//
+// Back-propagation reuses the same operation: the data gradient is the
+// convolution of the output gradient with the tap-flipped, channel-transposed
+// kernel; the weight gradient is, per tap, a 16 x 16 GEMM over the 512 voxels.
+// Each block writes its gradient to its own row of a partial buffer; a second
+// kernel sums the rows in a fixed order (deterministic), and Adam updates the
+// float32 master weights and re-rounds the bf16 copies.
+#include <algorithm>
+
+#include "itm_internal.hpp"
+
+namespace itm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kC = 16, kTaps = 27, kLayers = 4;
+constexpr int kNW = kRefineWeights;
+constexpr int kNP = kRefineParams;
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// LDS working set of one block
+struct RefineLds {
+    uint16_t x0[1000 * 4];          // network input, 10^3 grid, channels F, W/max_w, 0, 0
+    uint16_t act[3][512 * kC];      // outputs of layers 1..3 (inputs of 2..4), 8^3 x 16
+    uint16_t grad[2][512 * kC];     // back-propagated gradient, ping-pong
+    float centre[512];              // F of the block itself (float32), for the residual
+};
+
+// A operand: 16 voxels x 4 channels of a layer input for one tap.
+// layer 0 reads the haloed 10^3 grid, later layers the zero-padded 8^3 block.
+__device__ __forceinline__ bf16x4 a_operand(const RefineLds &L, const uint16_t *in, int layer, int vox,
+                                            int tap, int kq)
+{
+    const int x = vox & 7, y = (vox >> 3) & 7, z = vox >> 6;
+    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+    bf16x4 a = {0, 0, 0, 0};
+    if (layer == 0) {
+        if (kq == 0) {
+            const int u = (x + dx) + 10 * (y + dy) + 100 * (z + dz);
+            a = *reinterpret_cast<const bf16x4 *>(&L.x0[u * 4]);
+        }
+    } else {
+        const int ux = x + dx - 1, uy = y + dy - 1, uz = z + dz - 1;
+        if ((unsigned)ux < 8u && (unsigned)uy < 8u && (unsigned)uz < 8u)
+            a = *reinterpret_cast<const bf16x4 *>(&in[(ux + 8 * uy + 64 * uz) * kC + 4 * kq]);
+    }
+    return a;
+}
+
+// one wave's 8 tiles of a 3^3 convolution: acc[t] (lane: voxel 4 kq + r of tile
+// 8 w + t, channel lane & 15) = sum over taps of A(tap) x W(tap)
+__device__ __forceinline__ void conv_tiles(const RefineLds &L, const uint16_t *in, int layer,
+                                           const uint16_t *Wl, bool flip, int wave, int lane,
+                                           f32x4 acc[8])
+{
+    const int kq = lane >> 4, n = lane & 15;
+#pragma unroll
+    for (int t = 0; t < 8; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int tap = 0; tap < kTaps; tap++) {
+        const int wt = flip ? kTaps - 1 - tap : tap;
+        // B operand: 4 consecutive reduction channels of output column n
+        const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Wl[(wt * kC + n) * kC + 4 * kq]);
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+            const int vox = (wave * 8 + t) * 16 + n;
+            acc[t] = mfma16(a_operand(L, in, layer, vox, tap, kq), b, acc[t]);
+        }
+    }
+}
+
+// forward through the 4 layers; leaves activations in L.act and returns, for the
+// lanes with output channel 0, the residual delta of their 4 voxels per tile
+__device__ void refine_forward(RefineLds &L, const RefineParams &P, int wave, int lane, f32x4 delta[8])
+{
+    const int kq = lane >> 4, n = lane & 15;
+    f32x4 acc[8];
+    for (int l = 0; l < kLayers; l++) {
+        const uint16_t *in = l == 0 ? nullptr : L.act[l - 1];
+        conv_tiles(L, in, l, P.Wf + (size_t)l * kTaps * kC * kC, false, wave, lane, acc);
+        const float b = P.bias[l * kC + n];
+        if (l < kLayers - 1) {
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    L.act[l][vox * kC + n] = to_bf16(fmaxf(acc[t][r] + b, 0.0f));
+                }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) delta[t][r] = acc[t][r] + b;
+        }
+        __syncthreads();
+    }
+}
+
+// fill L.x0 / L.centre from a float32 input block [2][10^3] in global memory
+__device__ void load_input(RefineLds &L, const float *in)
+{
+    for (int u = threadIdx.x; u < 1000; u += blockDim.x) {
+        const float F = in[u], W = in[1000 + u];
+        uint16_t *d = &L.x0[u * 4];
+        d[0] = to_bf16(F);
+        d[1] = to_bf16(W);
+        d[2] = 0;
+        d[3] = 0;
+        const int x = u % 10, y = (u / 10) % 10, z = u / 100;
+        if (x >= 1 && x <= 8 && y >= 1 && y <= 8 && z >= 1 && z <= 8)
+            L.centre[(x - 1) + 8 * (y - 1) + 64 * (z - 1)] = F;
+    }
+}
+
+template <bool TRAIN>
+__global__ __launch_bounds__(256) void k_refine(RefineArgs a)
+{
+    __shared__ RefineLds L;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, n = lane & 15;
+    for (int64_t blk = blockIdx.x; blk < a.n; blk += gridDim.x) {
+        load_input(L, a.in + blk * 2000);
+        __syncthreads();
+        f32x4 delta[8];
+        refine_forward(L, a.P, wave, lane, delta);
+        // residual, clamp, loss gradient (lanes with output channel 0)
+        float sq = 0.0f, cnt = 0.0f;
+        if (TRAIN) {
+            for (int i = threadIdx.x; i < 512 * kC; i += blockDim.x) {
+                L.grad[0][i] = 0;
+                L.grad[1][i] = 0;
+            }
+            __syncthreads();
+        }
+        if (n == 0) {
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const float z = L.centre[vox] + delta[t][r];
+                    const float Fo = fminf(fmaxf(z, -1.0f), 1.0f);
+                    if (!TRAIN) {
+                        a.out[blk * 512 + vox] = Fo;
+                    } else {
+                        const bool m = a.mask[blk * 512 + vox] != 0;
+                        const float e = Fo - a.target[blk * 512 + vox];
+                        if (m) { sq += e * e; cnt += 1.0f; }
+                        const float g = (m && z > -1.0f && z < 1.0f) ? 2.0f * e : 0.0f;
+                        L.grad[0][vox * kC] = to_bf16(g);
+                        if (a.out) a.out[blk * 512 + vox] = Fo;
+                    }
+                }
+        }
+        if (!TRAIN) {
+            __syncthreads();
+            continue;
+        }
+        // loss partial: reduce over the wave, then the 4 waves
+        __shared__ float red[2][4];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            sq += __shfl_xor(sq, o, 64);
+            cnt += __shfl_xor(cnt, o, 64);
+        }
+        if (lane == 0) { red[0][wave] = sq; red[1][wave] = cnt; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            a.loss_part[blk * 2] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+            a.loss_part[blk * 2 + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+        }
+        float *gp = a.grad_part + blk * kNP;
+        int cur = 0;
+        for (int l = kLayers - 1; l >= 0; l--) {
+            const uint16_t *G = L.grad[cur];
+            // bias gradient: sum of the (bf16) output gradient over the voxels
+            if (threadIdx.x < kC) {
+                float s = 0.0f;
+                for (int v = 0; v < 512; v++) s += from_bf16(G[v * kC + threadIdx.x]);
+                gp[kNW + l * kC + threadIdx.x] = s;
+            }
+            // weight gradient, taps split over the waves: per tap a 16 x 16 GEMM
+            // over the 512 voxels (M = output channel, N = input channel)
+            const uint16_t *X = l == 0 ? nullptr : L.act[l - 1];
+            for (int tap = wave; tap < kTaps; tap += 4) {
+                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                for (int ks = 0; ks < 32; ks++) {
+                    bf16x4 av, bv;
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const int v = ks * 16 + 4 * kq + j;
+                        av[j] = (short)G[v * kC + n];
+                        const int x = v & 7, y = (v >> 3) & 7, z = v >> 6;
+                        uint16_t xv = 0;
+                        if (l == 0) {
+                            if (n < 4) xv = L.x0[((x + dx) + 10 * (y + dy) + 100 * (z + dz)) * 4 + n];
+                        } else {
+                            const int ux = x + dx - 1, uy = y + dy - 1, uz = z + dz - 1;
+                            if ((unsigned)ux < 8u && (unsigned)uy < 8u && (unsigned)uz < 8u)
+                                xv = X[(ux + 8 * uy + 64 * uz) * kC + n];
+                        }
+                        bv[j] = (short)xv;
+                    }
+                    acc = mfma16(av, bv, acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; r++) gp[((l * kTaps + tap) * kC + 4 * kq + r) * kC + n] = acc[r];
+            }
+            if (l == 0) break;
+            // data gradient into the previous layer's output, masked by its ReLU
+            f32x4 acc[8];
+            conv_tiles(L, G, 1, a.P.Wt + (size_t)l * kTaps * kC * kC, true, wave, lane, acc);
+            uint16_t *Gn = L.grad[cur ^ 1];
+            const uint16_t *A = L.act[l - 1];
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const bool on = from_bf16(A[vox * kC + n]) > 0.0f;
+                    Gn[vox * kC + n] = on ? to_bf16(acc[t][r]) : (uint16_t)0;
+                }
+            __syncthreads();
+            cur ^= 1;
+        }
+        __syncthreads();
+    }
+}
+
+// sum the per-block partial gradients in block order, divide by the batch's
+// count of supervised voxels
+__global__ void k_refine_reduce(const float *grad_part, const float *loss_part, int64_t n, float *grad,
+                                float *loss)
+{
+    float cnt = 0.0f;
+    for (int64_t b = 0; b < n; b++) cnt += loss_part[2 * b + 1];
+    const float inv = 1.0f / fmaxf(cnt, 1.0f);
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < kNP) {
+        float s = 0.0f;
+        for (int64_t b = 0; b < n; b++) s += grad_part[b * kNP + p];
+        grad[p] = s * inv;
+    }
+    if (p == 0) {
+        float sq = 0.0f;
+        for (int64_t b = 0; b < n; b++) sq += loss_part[2 * b];
+        loss[0] = sq * inv;
+    }
+}
+
+// Adam on float32 master weights, then the two bf16 copies
+__global__ void k_refine_adam(float *master, float *m, float *v, const float *grad, uint16_t *Wf,
+                              uint16_t *Wt, float *bias, float lr, float b1, float b2, float eps,
+                              float c1, float c2)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNP) return;
+    const float g = grad[p];
+    const float mm = b1 * m[p] + (1.0f - b1) * g;
+    const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+    m[p] = mm;
+    v[p] = vv;
+    const float w = master[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
+    master[p] = w;
+    if (p < kNW) {
+        Wf[p] = to_bf16(w);
+        const int ci = p % kC, co = (p / kC) % kC, lt = p / (kC * kC);
+        Wt[(lt * kC + ci) * kC + co] = to_bf16(w);
+    } else {
+        bias[p - kNW] = w;
+    }
+}
+
+// bf16 copies of a master vector (after a parameter upload)
+__global__ void k_refine_cast(const float *master, uint16_t *Wf, uint16_t *Wt, float *bias)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= kNP) return;
+    const float w = master[p];
+    if (p < kNW) {
+        Wf[p] = to_bf16(w);
+        const int ci = p % kC, co = (p / kC) % kC, lt = p / (kC * kC);
+        Wt[(lt * kC + ci) * kC + co] = to_bf16(w);
+    } else {
+        bias[p - kNW] = w;
+    }
+}
+
+// network input of a block from the volume: F and W / max_w on the 10^3 grid
+// around it; voxels of absent neighbour blocks read F = 1, W = 0
+template <int FMT>
+__global__ void k_refine_gather(HashView h, const void *sdf, const void *w, const int32_t *coords, int64_t n,
+                                float inv_max_w, float *out)
+{
+    using V = Vox<FMT>;
+    const auto *S = (const typename V::S *)sdf;
+    const auto *Wv = (const typename V::Wt *)w;
+    for (int64_t b = blockIdx.x; b < n; b += gridDim.x) {
+        const int kx = coords[3 * b], ky = coords[3 * b + 1], kz = coords[3 * b + 2];
+        for (int u = threadIdx.x; u < 1000; u += blockDim.x) {
+            const int vx = 8 * kx - 1 + u % 10, vy = 8 * ky - 1 + (u / 10) % 10, vz = 8 * kz - 1 + u / 100;
+            const int32_t p = find_block_direct(h, vx >> 3, vy >> 3, vz >> 3);
+            float F = 1.0f, Wf = 0.0f;
+            if (p >= 0) {
+                const int64_t i = (int64_t)p * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7);
+                F = V::to_f(S[i]);
+                Wf = V::w_to_f(Wv[i]) * inv_max_w;
+            }
+            out[b * 2000 + u] = F;
+            out[b * 2000 + 1000 + u] = Wf;
+        }
+    }
+}
+
+// Per-frame inference gate: every visible block whose largest weight is below
+// the threshold is refined; its network input is gathered straight from the
+// volume into LDS and the refined F goes to a side buffer (half precision,
+// indexed like the voxel block array) stamped with the frame number.
+template <int FMT>
+__global__ __launch_bounds__(256) void k_refine_gated(RefineGateArgs a)
+{
+    using V = Vox<FMT>;
+    __shared__ RefineLds L;
+    __shared__ int s_go;
+    const auto *S = (const typename V::S *)a.sdf;
+    const auto *Wv = (const typename V::Wt *)a.w;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, n = lane & 15;
+    const int n_vis = a.cnt->n_vis;
+    for (int bi = blockIdx.x; bi < n_vis; bi += gridDim.x) {
+        const int32_t e = a.vis_list[bi];
+        unsigned long long key;
+        int32_t ptr;
+        if (e < 2 * a.h.n_buckets) {
+            key = a.h.buckets[e >> 1].key[e & 1];
+            ptr = a.h.buckets[e >> 1].ptr[e & 1];
+        } else {
+            key = a.h.excess[e - 2 * a.h.n_buckets].key;
+            ptr = a.h.excess[e - 2 * a.h.n_buckets].ptr;
+        }
+        int kx, ky, kz;
+        unpack_key(key, kx, ky, kz);
+        // gate on the block's largest weight
+        if (threadIdx.x == 0) s_go = 0;
+        __syncthreads();
+        if (ptr >= 0)
+            for (int i = threadIdx.x; i < kBlockVox; i += blockDim.x)
+                if (V::w_to_f(Wv[(int64_t)ptr * kBlockVox + i]) >= a.w_threshold) s_go = 1;  // benign race
+        __syncthreads();
+        const bool skip = ptr < 0 || s_go != 0;
+        __syncthreads();                 // every thread has read s_go before it is reset
+        if (skip) continue;              // uniform over the workgroup
+        for (int u = threadIdx.x; u < 1000; u += blockDim.x) {
+            const int vx = 8 * kx - 1 + u % 10, vy = 8 * ky - 1 + (u / 10) % 10, vz = 8 * kz - 1 + u / 100;
+            const int32_t p = find_block_direct(a.h, vx >> 3, vy >> 3, vz >> 3);
+            float F = 1.0f, Wf = 0.0f;
+            if (p >= 0) {
+                const int64_t i = (int64_t)p * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7);
+                F = V::to_f(S[i]);
+                Wf = V::w_to_f(Wv[i]) * a.inv_max_w;
+            }
+            uint16_t *d = &L.x0[u * 4];
+            d[0] = to_bf16(F);
+            d[1] = to_bf16(Wf);
+            d[2] = 0;
+            d[3] = 0;
+            const int x = u % 10, y = (u / 10) % 10, z = u / 100;
+            if (x >= 1 && x <= 8 && y >= 1 && y <= 8 && z >= 1 && z <= 8)
+                L.centre[(x - 1) + 8 * (y - 1) + 64 * (z - 1)] = F;
+        }
+        __syncthreads();
+        f32x4 delta[8];
+        refine_forward(L, a.P, wave, lane, delta);
+        if (n == 0) {
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const float Fo = fminf(fmaxf(L.centre[vox] + delta[t][r], -1.0f), 1.0f);
+                    a.refined[(int64_t)ptr * kBlockVox + vox] = __float2half_rn(Fo);
+                }
+        }
+        if (threadIdx.x == 0) a.stamp[ptr] = a.frame;
+        __syncthreads();
+    }
+}
+
+hipError_t launch_refine_gated(int fmt, const RefineGateArgs &a, int grid, hipStream_t st)
+{
+    switch (fmt) {
+    case ITM_VOX_F32: k_refine_gated<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
+    case ITM_VOX_F16: k_refine_gated<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;
+    default: k_refine_gated<ITM_VOX_S16U8><<<grid, 256, 0, st>>>(a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_refine(const RefineArgs &a, bool train, int grid, hipStream_t st)
+{
+    if (train) k_refine<true><<<grid, 256, 0, st>>>(a);
+    else k_refine<false><<<grid, 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_reduce(const float *grad_part, const float *loss_part, int64_t n, float *grad,
+                                float *loss, hipStream_t st)
+{
+    k_refine_reduce<<<(kNP + 255) / 256, 256, 0, st>>>(grad_part, loss_part, n, grad, loss);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_adam(float *master, float *m, float *v, const float *grad, uint16_t *Wf, uint16_t *Wt,
+                              float *bias, float lr, int step, hipStream_t st)
+{
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    k_refine_adam<<<(kNP + 255) / 256, 256, 0, st>>>(master, m, v, grad, Wf, Wt, bias, lr, b1, b2, 1e-8f, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_cast(const float *master, uint16_t *Wf, uint16_t *Wt, float *bias, hipStream_t st)
+{
+    k_refine_cast<<<(kNP + 255) / 256, 256, 0, st>>>(master, Wf, Wt, bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_refine_gather(int fmt, const HashView &h, const void *sdf, const void *w, const int32_t *coords,
+                                int64_t n, float inv_max_w, float *out, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>(n, 4096);
+    if (grid <= 0) return hipSuccess;
+    switch (fmt) {
+    case ITM_VOX_F32: k_refine_gather<ITM_VOX_F32><<<grid, 256, 0, st>>>(h, sdf, w, coords, n, inv_max_w, out); break;
+    case ITM_VOX_F16: k_refine_gather<ITM_VOX_F16><<<grid, 256, 0, st>>>(h, sdf, w, coords, n, inv_max_w, out); break;
+    default: k_refine_gather<ITM_VOX_S16U8><<<grid, 256, 0, st>>>(h, sdf, w, coords, n, inv_max_w, out); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace itm

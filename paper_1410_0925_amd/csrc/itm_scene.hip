@@ -46,10 +46,17 @@ int64_t next_pow2(int64_t x)
 
 constexpr int kProfSlots = 4096;
 
-// macro-cell bitmap: a power of two of bits, half the bucket count, at least 2^16
-int64_t macro_words(int64_t n_buckets) { return std::max<int64_t>(n_buckets / 2, 1 << 16) / 32; }
-
 }  // namespace
+
+struct itm_refiner {
+    hipStream_t stream = nullptr;
+    float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *loss = nullptr, *bias = nullptr;
+    uint16_t *Wf = nullptr, *Wt = nullptr;
+    float *grad_part = nullptr, *loss_part = nullptr;
+    int64_t part_cap = 0;
+    int step = 0;
+    int num_cu = 0;
+};
 
 struct itm_scene {
     float s, mu;
@@ -73,9 +80,14 @@ struct itm_scene {
     Counters *cnt = nullptr;
     uint32_t *occ = nullptr;
     int64_t occ_words = 0;
-    int64_t macro_bits = 0;
     int32_t *hint_host = nullptr;  // mapped pinned word written by k_compact
     int32_t *hint_dev = nullptr;
+
+    itm_refiner *refiner = nullptr;   // not owned
+    float refine_w_threshold = 0.0f;
+    __half *refined = nullptr;        // [vba_cap][512], allocated on attach
+    int32_t *stamp = nullptr;         // [vba_cap]
+    int32_t frame = 0;
 
     bool prof = false;
     std::vector<hipEvent_t> ev;     // 2 per slot
@@ -105,6 +117,8 @@ void release(itm_scene *sc)
     (void)hipFree(sc->set_list);
     (void)hipFree(sc->cnt);
     (void)hipFree(sc->occ);
+    (void)hipFree(sc->refined);
+    (void)hipFree(sc->stamp);
     if (sc->hint_host) (void)hipHostFree(sc->hint_host);
     delete sc;
 }
@@ -171,7 +185,6 @@ HashView hash_view(const itm_scene *sc)
     h.excess = sc->excess;
     h.occ = sc->occ;
     h.macro = sc->occ + sc->occ_words;
-    h.macro_mask = (uint32_t)(sc->macro_bits - 1);
     h.mask = sc->mask;
     h.n_buckets = (int32_t)sc->n_buckets;
     h.n_excess = (int32_t)sc->n_excess;
@@ -288,7 +301,7 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
         dev_alloc((void **)&sc->set, sizeof(unsigned long long) * sc->set_size, "claim set") ||
         dev_alloc((void **)&sc->set_list, sizeof(int32_t) * sc->set_size, "claim list") ||
         dev_alloc((void **)&sc->cnt, sizeof(Counters), "counters") ||
-        dev_alloc((void **)&sc->occ, sizeof(uint32_t) * ((n_buckets + 31) / 32 + macro_words(n_buckets)),
+        dev_alloc((void **)&sc->occ, sizeof(uint32_t) * ((n_buckets + 31) / 32 + kMacroWords),
                   "occupancy bitmaps")) {
         release(sc);
         return nullptr;
@@ -302,9 +315,8 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
         *sc->hint_host = 0;
     }
     sc->occ_words = (n_buckets + 31) / 32;
-    sc->macro_bits = macro_words(n_buckets) * 32;
     hipError_t e = launch_init(sc->buckets, n_buckets, sc->excess, n_excess, sc->vis, sc->vis_bytes,
-                               sc->set, sc->set_size, sc->occ, sc->occ_words + macro_words(n_buckets),
+                               sc->set, sc->set_size, sc->occ, sc->occ_words + kMacroWords,
                                sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     if (e != hipSuccess) {
@@ -379,6 +391,24 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
         int64_t grid = std::max<int64_t>((last + last / 4 + 3) / 4, (int64_t)sc->num_cu * 2);
         grid = std::min<int64_t>(grid, (int64_t)sc->num_cu * 64);
         HIP_TRY(launch_integrate(sc->fmt, ia, (int)grid, sc->stream));
+    }
+    sc->frame++;
+    if (sc->refiner) {
+        RefineGateArgs ra;
+        ra.P.Wf = sc->refiner->Wf;
+        ra.P.Wt = sc->refiner->Wt;
+        ra.P.bias = sc->refiner->bias;
+        ra.h = h;
+        ra.vis_list = sc->vis_list;
+        ra.cnt = sc->cnt;
+        ra.sdf = sc->sdf;
+        ra.w = sc->w;
+        ra.inv_max_w = 1.0f / (float)sc->max_w;
+        ra.w_threshold = sc->refine_w_threshold;
+        ra.refined = sc->refined;
+        ra.stamp = sc->stamp;
+        ra.frame = sc->frame;
+        HIP_TRY(launch_refine_gated(sc->fmt, ra, sc->num_cu * 2, sc->stream));
     }
     return ITM_OK;
 }
@@ -528,6 +558,219 @@ itm_status itm_profile_read(itm_scene *sc, double *ms, int64_t *launches)
         launches[k] = sc->prof_n[k];
         sc->prof_ms[k] = 0;
         sc->prof_n[k] = 0;
+    }
+    return ITM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// learned refiner
+// ---------------------------------------------------------------------------
+static void refiner_free(itm_refiner *r)
+{
+    if (!r) return;
+    (void)hipStreamSynchronize(r->stream);
+    for (void *p : {(void *)r->master, (void *)r->m, (void *)r->v, (void *)r->grad, (void *)r->loss,
+                    (void *)r->bias, (void *)r->Wf, (void *)r->Wt, (void *)r->grad_part, (void *)r->loss_part})
+        (void)hipFree(p);
+    delete r;
+}
+
+itm_refiner *itm_refiner_create(const float *params, void *hip_stream)
+{
+    if (!params) {
+        fail(ITM_ERR_ARG, "NULL parameter vector");
+        return nullptr;
+    }
+    itm_refiner *r = new (std::nothrow) itm_refiner();
+    if (!r) {
+        fail(ITM_ERR_OOM, "host allocation failed");
+        return nullptr;
+    }
+    r->stream = (hipStream_t)hip_stream;
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        fail(ITM_ERR_HIP, "no HIP device");
+        refiner_free(r);
+        return nullptr;
+    }
+    r->num_cu = prop.multiProcessorCount;
+    const size_t P = sizeof(float) * kRefineParams;
+    if (dev_alloc((void **)&r->master, P, "refiner master") || dev_alloc((void **)&r->m, P, "adam m") ||
+        dev_alloc((void **)&r->v, P, "adam v") || dev_alloc((void **)&r->grad, P, "gradient") ||
+        dev_alloc((void **)&r->loss, sizeof(float), "loss") ||
+        dev_alloc((void **)&r->bias, sizeof(float) * 4 * 16, "bias") ||
+        dev_alloc((void **)&r->Wf, sizeof(uint16_t) * kRefineWeights, "bf16 weights") ||
+        dev_alloc((void **)&r->Wt, sizeof(uint16_t) * kRefineWeights, "bf16 weights^T")) {
+        refiner_free(r);
+        return nullptr;
+    }
+    hipError_t e = hipMemcpyAsync(r->master, params, P, hipMemcpyHostToDevice, r->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(r->m, 0, P, r->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(r->v, 0, P, r->stream);
+    if (e == hipSuccess) e = launch_refine_cast(r->master, r->Wf, r->Wt, r->bias, r->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(r->stream);
+    if (e != hipSuccess) {
+        fail(ITM_ERR_HIP, "refiner initialisation failed: %s", hipGetErrorString(e));
+        refiner_free(r);
+        return nullptr;
+    }
+    return r;
+}
+
+void itm_refiner_destroy(itm_refiner *r) { refiner_free(r); }
+
+itm_status itm_refiner_set_stream(itm_refiner *r, void *hip_stream)
+{
+    if (!r) return fail(ITM_ERR_ARG, "NULL refiner");
+    r->stream = (hipStream_t)hip_stream;
+    return ITM_OK;
+}
+
+itm_status itm_refiner_get_params(itm_refiner *r, float *params)
+{
+    if (!r || !params) return fail(ITM_ERR_ARG, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(params, r->master, sizeof(float) * kRefineParams, hipMemcpyDeviceToHost, r->stream));
+    HIP_TRY(hipStreamSynchronize(r->stream));
+    return ITM_OK;
+}
+
+static RefineParams refiner_params(const itm_refiner *r)
+{
+    RefineParams P;
+    P.Wf = r->Wf;
+    P.Wt = r->Wt;
+    P.bias = r->bias;
+    return P;
+}
+
+itm_status itm_refiner_forward(itm_refiner *r, const float *in, int64_t n, float *out)
+{
+    if (!r || (n > 0 && (!in || !out)) || n < 0) return fail(ITM_ERR_ARG, "bad refiner forward arguments");
+    if (n == 0) return ITM_OK;
+    RefineArgs a = {};
+    a.P = refiner_params(r);
+    a.in = in;
+    a.n = n;
+    a.out = out;
+    HIP_TRY(launch_refine(a, false, (int)std::min<int64_t>(n, (int64_t)r->num_cu * 2), r->stream));
+    return ITM_OK;
+}
+
+static itm_status refiner_grad(itm_refiner *r, const float *in, const float *target, const uint8_t *mask,
+                               int64_t n)
+{
+    if (!r || n <= 0 || !in || !target || !mask) return fail(ITM_ERR_ARG, "bad refiner gradient arguments");
+    if (n > r->part_cap) {
+        HIP_TRY(hipStreamSynchronize(r->stream));
+        (void)hipFree(r->grad_part);
+        (void)hipFree(r->loss_part);
+        r->grad_part = nullptr;
+        r->loss_part = nullptr;
+        r->part_cap = 0;
+        if (dev_alloc((void **)&r->grad_part, sizeof(float) * kRefineParams * (size_t)n, "gradient partials") ||
+            dev_alloc((void **)&r->loss_part, sizeof(float) * 2 * (size_t)n, "loss partials"))
+            return ITM_ERR_OOM;
+        r->part_cap = n;
+    }
+    RefineArgs a = {};
+    a.P = refiner_params(r);
+    a.in = in;
+    a.n = n;
+    a.target = target;
+    a.mask = mask;
+    a.grad_part = r->grad_part;
+    a.loss_part = r->loss_part;
+    HIP_TRY(launch_refine(a, true, (int)std::min<int64_t>(n, (int64_t)r->num_cu * 2), r->stream));
+    HIP_TRY(launch_refine_reduce(r->grad_part, r->loss_part, n, r->grad, r->loss, r->stream));
+    return ITM_OK;
+}
+
+itm_status itm_refiner_gradient(itm_refiner *r, const float *in, const float *target, const uint8_t *mask,
+                                int64_t n, float *grad, float *loss)
+{
+    if (itm_status st = refiner_grad(r, in, target, mask, n)) return st;
+    if (grad)
+        HIP_TRY(hipMemcpyAsync(grad, r->grad, sizeof(float) * kRefineParams, hipMemcpyDeviceToDevice, r->stream));
+    if (loss) HIP_TRY(hipMemcpyAsync(loss, r->loss, sizeof(float), hipMemcpyDeviceToDevice, r->stream));
+    return ITM_OK;
+}
+
+itm_status itm_refiner_train_step(itm_refiner *r, const float *in, const float *target, const uint8_t *mask,
+                                  int64_t n, float lr, float *loss)
+{
+    if (!(lr > 0)) return fail(ITM_ERR_ARG, "learning rate must be > 0");
+    if (itm_status st = refiner_grad(r, in, target, mask, n)) return st;
+    r->step++;
+    HIP_TRY(launch_refine_adam(r->master, r->m, r->v, r->grad, r->Wf, r->Wt, r->bias, lr, r->step, r->stream));
+    if (loss) HIP_TRY(hipMemcpyAsync(loss, r->loss, sizeof(float), hipMemcpyDeviceToDevice, r->stream));
+    return ITM_OK;
+}
+
+itm_status itm_gather_blocks(itm_scene *sc, const int32_t *coords, int64_t n, float *out)
+{
+    if (!sc || n < 0 || (n > 0 && (!coords || !out))) return fail(ITM_ERR_ARG, "bad gather arguments");
+    HIP_TRY(launch_refine_gather(sc->fmt, hash_view(sc), sc->sdf, sc->w, coords, n, 1.0f / (float)sc->max_w, out,
+                                 sc->stream));
+    return ITM_OK;
+}
+
+itm_status itm_scene_set_refiner(itm_scene *sc, itm_refiner *r, float w_threshold)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    if (r && !(w_threshold > 0)) return fail(ITM_ERR_ARG, "weight threshold must be > 0");
+    if (r && !sc->refined) {
+        if (dev_alloc((void **)&sc->refined, sizeof(__half) * kBlockVox * (size_t)sc->vba_cap, "refined F") ||
+            dev_alloc((void **)&sc->stamp, sizeof(int32_t) * (size_t)sc->vba_cap, "refine stamps"))
+            return ITM_ERR_OOM;
+        HIP_TRY(hipMemsetAsync(sc->stamp, 0, sizeof(int32_t) * (size_t)sc->vba_cap, sc->stream));
+    }
+    sc->refiner = r;
+    sc->refine_w_threshold = w_threshold;
+    return ITM_OK;
+}
+
+itm_status itm_export_blocks_refined(itm_scene *sc, int32_t *coords, float *sdf, uint8_t *refined,
+                                     int64_t capacity, int64_t *n_blocks)
+{
+    if (!sc || !n_blocks) return fail(ITM_ERR_ARG, "NULL scene or n_blocks");
+    if (itm_status st = itm_export_blocks(sc, coords, sdf, nullptr, capacity, n_blocks)) return st;
+    if (!coords || !sdf || !sc->refined || *n_blocks == 0) {
+        if (refined && coords) std::memset(refined, 0, (size_t)*n_blocks);
+        return ITM_OK;
+    }
+    // block pointers of the exported (sorted) blocks
+    std::vector<Bucket> hb(sc->n_buckets);
+    std::vector<Excess> hx(std::max<int64_t>(sc->n_excess, 1));
+    HIP_TRY(hipMemcpyAsync(hb.data(), sc->buckets, sizeof(Bucket) * sc->n_buckets, hipMemcpyDeviceToHost,
+                           sc->stream));
+    if (sc->n_excess)
+        HIP_TRY(hipMemcpyAsync(hx.data(), sc->excess, sizeof(Excess) * sc->n_excess, hipMemcpyDeviceToHost,
+                               sc->stream));
+    std::vector<int32_t> stamps(sc->vba_cap);
+    HIP_TRY(hipMemcpyAsync(stamps.data(), sc->stamp, sizeof(int32_t) * sc->vba_cap, hipMemcpyDeviceToHost,
+                           sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    auto ptr_of = [&](int32_t x, int32_t y, int32_t z) -> int32_t {
+        const unsigned long long key = kKeyValid | (unsigned long long)(uint16_t)x |
+                                       ((unsigned long long)(uint16_t)y << 16) |
+                                       ((unsigned long long)(uint16_t)z << 32);
+        const uint32_t b = (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u)) & sc->mask;
+        if (hb[b].key[0] == key) return hb[b].ptr[0];
+        if (hb[b].key[1] == key) return hb[b].ptr[1];
+        for (int32_t i = hb[b].head; i >= 0; i = hx[i].next)
+            if (hx[i].key == key) return hx[i].ptr;
+        return -1;
+    };
+    std::vector<__half> blk(kBlockVox);
+    for (int64_t i = 0; i < *n_blocks; i++) {
+        const int32_t p = ptr_of(coords[3 * i], coords[3 * i + 1], coords[3 * i + 2]);
+        const bool r = p >= 0 && stamps[p] == sc->frame && sc->frame > 0;
+        if (refined) refined[i] = r ? 1 : 0;
+        if (!r) continue;
+        HIP_TRY(hipMemcpy(blk.data(), sc->refined + (size_t)p * kBlockVox, sizeof(__half) * kBlockVox,
+                          hipMemcpyDeviceToHost));
+        for (int l = 0; l < kBlockVox; l++) sdf[i * kBlockVox + l] = __half2float(blk[l]);
     }
     return ITM_OK;
 }
