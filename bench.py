@@ -27,6 +27,35 @@ SDF_BYTES = {"f32": 4, "f16": 2, "s16u8": 2}
 VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 
 
+# Hardware byte counters of the kernels on this workload, per dispatch, from
+#   rocprofv3 --pmc FETCH_SIZE (resp. WRITE_SIZE) -- python3 bench.py --steps 20
+#   --warmup 10 --no-cpu-baseline --no-learned --no-events --calib-copy-mb 256
+# (summaries under profiles/).  The same counters read for the 256 MiB reference
+# copy give the scale factors: FETCH_SIZE reports half of the bytes read, WRITE_SIZE
+# all of the bytes written.  `src` is the SHA-256 of the kernel's source files when
+# the counters were taken; a changed kernel reports traffic null.
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.75, 262144.0 / 262144.0
+TRAFFIC_KIB = {}
+
+
+def kernel_source_sha(name):
+    import hashlib
+    files = {"alloc": "itm_alloc.hip", "compact": "itm_alloc.hip", "integrate": "itm_integrate.hip",
+             "raycast": "itm_raycast.hip"}[name]
+    h = hashlib.sha256()
+    for f in (files, "itm_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_1410_0925_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_bytes(name, fmt, workload):
+    t = TRAFFIC_KIB.get((name, fmt, workload))
+    if t is None or t["src"] != kernel_source_sha(name):
+        return None
+    return 1024.0 * (t["fetch"] * FETCH_SCALE + t["write"] * WRITE_SCALE)
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -50,6 +79,49 @@ def kernel_bytes(name, fmt, W, H, launches, vis_total, upd_total, n_entries):
         # the frame's visible blocks) + one bucket record each
         return 32.0 * W * H + vis * (512.0 * SDF_BYTES[fmt] + 32.0)
     return 0.0
+
+
+# algorithmic FLOPs of the refiner per block (multiply-adds x 2 over real channels):
+# layer 1 2->16, layers 2-3 16->16, layer 4 16->1, each 512 outputs x 27 taps
+REFINE_FWD_FLOP = 2 * 512 * 27 * (2 * 16 + 16 * 16 + 16 * 16 + 16 * 1)
+# backward: weight gradients of all layers + data gradients of layers 2-4
+REFINE_BWD_FLOP = REFINE_FWD_FLOP + 2 * 512 * 27 * (16 * 16 + 16 * 16 + 16 * 1)
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def learned_leg(itm, torch, steps=20, batch=256):
+    """Time training steps and forward passes of the refiner on random blocks."""
+    import time as _t
+    rng = np.random.default_rng(0)
+    p = (rng.standard_normal(itm.ITM_REFINE_PARAMS) * 0.05).astype(np.float32)
+    ref = itm.Refiner(p)
+    x = torch.rand((batch, 2000), device="cuda")
+    t = torch.rand((batch, 512), device="cuda") * 2 - 1
+    m = torch.ones((batch, 512), dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        ref.train_step(x, t, m, 1e-4)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(steps):
+        ref.train_step(x, t, m, 1e-4)
+    torch.cuda.synchronize()
+    dt_train = (_t.perf_counter() - t0) / steps
+    out = torch.empty((batch, 512), device="cuda")
+    for _ in range(3):
+        ref.forward(x, out)
+    torch.cuda.synchronize()
+    t0 = _t.perf_counter()
+    for _ in range(steps):
+        ref.forward(x, out)
+    torch.cuda.synchronize()
+    dt_fwd = (_t.perf_counter() - t0) / steps
+    ref.close()
+    tr = batch * (REFINE_FWD_FLOP + REFINE_BWD_FLOP) / dt_train / 1e12
+    fw = batch * REFINE_FWD_FLOP / dt_fwd / 1e12
+    return {"batch_blocks": batch, "train_step_ms": dt_train * 1e3, "train_TFLOPs": tr,
+            "forward_ms": dt_fwd * 1e3, "forward_TFLOPs": fw,
+            "frac_bf16_peak_train": tr / BF16_PEAK_TFLOPS, "frac_bf16_peak_forward": fw / BF16_PEAK_TFLOPS,
+            "flop_model": "algorithmic: real channels only (layer 1: 2 in, layer 4: 1 out)"}
 
 
 def cpu_baseline(stream, seconds):
@@ -83,7 +155,10 @@ def main():
     ap.add_argument("--fmt", default="f32", choices=sorted(SDF_BYTES))
     ap.add_argument("--workload", default="vga", choices=["vga", "large", "tiny"])
     ap.add_argument("--no-events", action="store_true", help="skip per-kernel HIP events")
+    ap.add_argument("--event-every", type=int, default=10,
+                    help="record per-kernel HIP events on every n-th timed frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the refiner timing leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, copy a buffer of this size once "
@@ -122,15 +197,20 @@ def main():
         sc.raycast(K, st.T_wc[f], pts, nrm)
     torch.cuda.synchronize()
     s0 = sc.stats()
-    if not args.no_events:
-        sc.profile(True)
-        sc.profile_read()
+    sc.profile_read()
     torch.cuda.synchronize()
+    # events bracket every launch of every n-th frame (they cost GPU idle time,
+    # so not every frame carries them)
     t_start = time.perf_counter()
     for i in range(args.steps):
         f = args.warmup + i
+        ev = not args.no_events and i % args.event_every == 0
+        if ev:
+            sc.profile(True)
         sc.integrate(depth[f], K, st.T_wc[f])
         sc.raycast(K, st.T_wc[f], pts, nrm)
+        if ev:
+            sc.profile(False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
     prof = sc.profile_read() if not args.no_events else {}
@@ -153,18 +233,21 @@ def main():
         if launches == 0:
             continue
         avg_ms = ms / launches
-        b = kernel_bytes(name, args.fmt, W, H, launches, vis_total, upd_total, s1["n_entries"])
+        # algorithmic bytes per launch over all timed frames
+        b = kernel_bytes(name, args.fmt, W, H, args.steps, vis_total, upd_total, s1["n_entries"])
         gbs = b / (avg_ms * 1e-3) / 1e9
-        kernels[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches": launches,
+        tr = traffic_bytes(name, args.fmt, args.workload)
+        kernels[name] = {"avg_us": round(avg_ms * 1e3, 3), "launches_timed": launches,
                          "bytes_per_launch": round(b), "achieved_GBs": round(gbs, 1),
-                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic_bytes": None if tr is None else round(tr)}
         if best is None or ms > prof[best][0]:
             best = name
     roofline = None
     if best:
         k = kernels[best]
         roofline = {"bound": "hbm", "kernel": best, "achieved": k["achieved_GBs"], "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": k["frac_hbm"], "traffic": None}
+                    "unit": "GB/s", "frac": k["frac_hbm"], "traffic": k["traffic_bytes"]}
     gpu_ms = sum(ms for ms, _ in prof.values()) if prof else None
     out = {
         "metric": METRIC,
@@ -191,6 +274,9 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if not args.no_learned:
+        log("learned form: refiner training steps and forward passes")
+        out["learned"] = learned_leg(itm, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(st, args.cpu_seconds)

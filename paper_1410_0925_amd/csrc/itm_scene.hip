@@ -542,10 +542,7 @@ itm_status itm_profile_enable(itm_scene *sc, int enable)
         sc->ev_kernel.resize(kProfSlots);
         for (auto &e : sc->ev) HIP_TRY(hipEventCreate(&e));
     }
-    if (!enable && sc->prof) {
-        if (itm_status st = prof_flush(sc)) return st;
-    }
-    sc->prof = enable != 0;
+    sc->prof = enable != 0;   // recorded events are collected by itm_profile_read
     return ITM_OK;
 }
 
