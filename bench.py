@@ -40,8 +40,8 @@ TRAFFIC_KIB = {}
 
 def kernel_source_sha(name):
     import hashlib
-    files = {"alloc": "itm_alloc.hip", "compact": "itm_alloc.hip", "integrate": "itm_integrate.hip",
-             "raycast": "itm_raycast.hip"}[name]
+    files = {"alloc": "itm_alloc.hip", "integrate": "itm_integrate.hip", "raycast": "itm_raycast.hip",
+             "refine": "itm_refine.hip"}[name]
     h = hashlib.sha256()
     for f in (files, "itm_internal.hpp"):
         with open(os.path.join(ROOT, "paper_1410_0925_amd", "csrc", f), "rb") as fh:
@@ -66,14 +66,12 @@ def kernel_bytes(name, fmt, W, H, launches, vis_total, upd_total, n_entries):
         return 0.0
     vis = vis_total / launches
     if name == "integrate":
-        # read + write F and W of every updated voxel
-        return 2.0 * VOX_BYTES[fmt] * upd_total / launches
+        # read + write F and W of every updated voxel; scan every visibility flag
+        # and clear the set ones (the visible-list stage fused in)
+        return 2.0 * VOX_BYTES[fmt] * upd_total / launches + float(n_entries) + vis
     if name == "alloc":
         # the depth image + one 32-byte bucket record per visible block + flags
         return 4.0 * W * H + 32.0 * vis + vis
-    if name == "compact":
-        # read every flag, clear the set ones, write the list
-        return float(n_entries) + vis + 4.0 * vis
     if name == "raycast":
         # two float4 maps out + the F values of the blocks in view (estimated by
         # the frame's visible blocks) + one bucket record each

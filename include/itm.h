@@ -145,7 +145,7 @@ itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
 /* Per-kernel timing with HIP events recorded on the scene's stream around every
  * launch while enabled (toggling does not synchronise; events recorded while
  * enabled are kept until read).  Kernel ids: 0 allocation, 1 visible-list
- * compaction, 2 integration, 3 raycast. */
+ * compaction fused with integration, 2 raycast, 3 refiner gate. */
 #define ITM_KERNEL_COUNT 4
 itm_status itm_profile_enable(itm_scene *scene, int enable);
 /* Synchronises, then writes the summed milliseconds and launch counts per kernel

@@ -15,7 +15,7 @@
 //   * a block whose excess claim finds the list exhausted is dropped and counted
 //     once per frame.
 // The paper's stages two (reserve a voxel block) and three (visible list) are the
-// atomic pop at a winning claim and k_compact below.
+// atomic pop at a winning claim and the flag scan at the start of k_integrate.
 #include "itm_internal.hpp"
 
 namespace itm {
@@ -49,6 +49,8 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
             if (i == 0) atomicOr(&h.occ[b >> 5], 1u << (b & 31));  // slot 0 fills first
             const uint32_t m = macro_index(bx, by, bz);
             atomicOr(&h.macro[m >> 5], 1u << (m & 31));
+            const uint32_t f = bfilt_index(bx, by, bz);
+            atomicOr(&h.bfilt[f >> 5], 1u << (f & 31));
             return 2 * (int32_t)b + i;
         }
         if (old == key) return 2 * (int32_t)b + i;
@@ -66,7 +68,7 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
         if (old == key) return -1;  // claimed by another lane, which flags it
         slot = (slot + 1) & a.set_mask;
     }
-    a.set_list[atomicAdd(&a.cnt->set_used, 1)] = (int32_t)slot;
+    a.set_list[atomicAdd(&a.cnt->set_used[a.parity], 1)] = (int32_t)slot;
     // Earlier frames' chain entries were all seen by the walk above; entries
     // linked during this frame belong to other claimed blocks.  So the block is
     // absent: take an excess entry.
@@ -81,6 +83,8 @@ __device__ static int32_t find_or_insert(const AllocArgs &a, int bx, int by, int
     {
         const uint32_t m = macro_index(bx, by, bz);
         atomicOr(&h.macro[m >> 5], 1u << (m & 31));
+        const uint32_t f = bfilt_index(bx, by, bz);
+        atomicOr(&h.bfilt[f >> 5], 1u << (f & 31));
     }
     // link at the end of the chain; every failed compare-and-swap means another
     // claimant linked first, so the walk moves on and terminates
@@ -97,8 +101,12 @@ __global__ __launch_bounds__(256) void k_alloc(AllocArgs a)
 {
     const FrameGeom &g = a.fg;
     if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) a.cnt->n_vis = 0;                 // filled by k_compact
-        if (threadIdx.x < kStripes) a.cnt->upd[0][threadIdx.x][0] = 0;  // filled by k_integrate
+        // per-frame counters, filled by k_integrate
+        if (threadIdx.x == 0) a.cnt->n_vis = 0;
+        if (threadIdx.x < kStripes) {
+            a.cnt->upd[0][threadIdx.x][0] = 0;
+            a.cnt->vis[0][threadIdx.x][0] = 0;
+        }
     }
     int tx, ty;
     if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;
@@ -164,79 +172,6 @@ __global__ __launch_bounds__(256) void k_alloc(AllocArgs a)
 hipError_t launch_alloc(const AllocArgs &a, hipStream_t st)
 {
     k_alloc<<<xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16)), 256, 0, st>>>(a);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// k_compact: visible-list compaction (stage three).  Each lane takes 16 flag
-// bytes, a wave prefix sum of the per-lane counts gives every lane its place,
-// one atomic per wave reserves the wave's range, and the flags are cleared.  The
-// same pass clears the claim-set slots used by the frame.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int bytes_set(uint32_t x) { return (int)((x * 0x01010101u) >> 24); }
-
-constexpr int kCompactPerThread = 4;   // 16-byte flag chunks per thread and pass
-
-__global__ __launch_bounds__(256) void k_compact(CompactArgs a)
-{
-    __shared__ int wave_tot[256 / kWave];
-    __shared__ int wg_base;
-    const int tid = blockIdx.x * blockDim.x + threadIdx.x;
-    const int stride = gridDim.x * blockDim.x;
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = threadIdx.x / kWave;
-    const int su = a.cnt->set_used;
-    for (int i = tid; i < su; i += stride) a.set[a.set_list[i]] = 0ull;
-
-    const int span = blockDim.x * kCompactPerThread;
-    for (int base = blockIdx.x * span; base < a.n_chunks; base += gridDim.x * span) {
-        uint4 v[kCompactPerThread];
-        int c = 0;
-#pragma unroll
-        for (int j = 0; j < kCompactPerThread; j++) {
-            const int chunk = base + j * blockDim.x + threadIdx.x;
-            v[j] = chunk < a.n_chunks ? a.vis4[chunk] : make_uint4(0, 0, 0, 0);
-            c += bytes_set(v[j].x) + bytes_set(v[j].y) + bytes_set(v[j].z) + bytes_set(v[j].w);
-        }
-        // workgroup exclusive scan: wave scan, then the wave totals through LDS
-        int incl = c;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(incl, o, kWave);
-            if (lane >= o) incl += y;
-        }
-        if (lane == kWave - 1) wave_tot[wave] = incl;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int t = 0;
-            for (int w = 0; w < (int)(blockDim.x / kWave); w++) {
-                const int x = wave_tot[w];
-                wave_tot[w] = t;
-                t += x;
-            }
-            wg_base = t > 0 ? atomicAdd(&a.cnt->n_vis, t) : 0;  // one atomic per workgroup
-        }
-        __syncthreads();
-        int k = wg_base + wave_tot[wave] + incl - c;
-        __syncthreads();  // wave_tot / wg_base are rewritten by the next pass
-        if (c > 0) {
-#pragma unroll
-            for (int j = 0; j < kCompactPerThread; j++) {
-                const int chunk = base + j * blockDim.x + threadIdx.x;
-                const uint32_t w4[4] = {v[j].x, v[j].y, v[j].z, v[j].w};
-                if ((w4[0] | w4[1] | w4[2] | w4[3]) == 0u) continue;
-#pragma unroll
-                for (int q = 0; q < 16; q++)
-                    if ((w4[q >> 2] >> (8 * (q & 3))) & 0xffu) a.vis_list[k++] = chunk * 16 + q;
-                a.vis4[chunk] = make_uint4(0, 0, 0, 0);
-            }
-        }
-    }
-}
-
-hipError_t launch_compact(const CompactArgs &a, int grid, hipStream_t st)
-{
-    k_compact<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

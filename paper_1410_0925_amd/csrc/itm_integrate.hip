@@ -1,8 +1,9 @@
 // Integration (section "Integration", computeUpdatedVoxelDepthInfo) over the
 // voxels of the frame's visible blocks.
 //
-// One wave per visible block, grid-stride over the device-side visible count (no
-// host read-back).  Lane l owns voxels 4l..4l+3 and 256+4l..256+4l+3 of the block,
+// One wave per visible block (the workgroups find their blocks by scanning the
+// visibility flags, so no count is read back).  Lane l owns voxels 4l..4l+3 and
+// 256+4l..256+4l+3 of the block,
 // so every voxel load or store instruction of a wave covers one contiguous range
 // (16 B per lane in the float form).  A lane first decides, for its 8 voxels,
 // whether each is updated -- that needs only the voxel's position and the depth
@@ -100,110 +101,168 @@ struct Group4<ITM_VOX_S16U8> {
     }
 };
 
+// one visible block (entry e) by one wave; returns the lane's updated voxels
 template <int FMT>
-__global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a)
+__device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane)
 {
     const FrameGeom &g = a.fg;
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt->set_used = 0;  // claim set drained by k_compact
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave_in_wg = threadIdx.x / kWave;
-    const int waves_per_wg = blockDim.x / kWave;
-    const int n_vis = a.cnt->n_vis;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        a.cnt->n_vis_last = n_vis;
-        a.cnt->vis_total += (unsigned long long)n_vis;
-        if (a.host_hint) *(volatile int32_t *)a.host_hint = n_vis;  // sizes the next launch
+    unsigned long long key;
+    int32_t ptr;
+    if (e < 2 * a.h.n_buckets) {
+        key = a.h.buckets[e >> 1].key[e & 1];
+        ptr = a.h.buckets[e >> 1].ptr[e & 1];
+    } else {
+        key = a.h.excess[e - 2 * a.h.n_buckets].key;
+        ptr = a.h.excess[e - 2 * a.h.n_buckets].ptr;
     }
-    const float mu = g.mu_f;
-    const float inv_mu = 1.0f / mu;
+    if (ptr < 0) return 0;  // cannot happen: every flagged entry owns a block
+    int kx, ky, kz;
+    unpack_key(key, kx, ky, kz);
+    // block origin in camera coordinates, binary64 -> binary32 pair
+    const double o0 = (double)(8 * kx) * g.s, o1 = (double)(8 * ky) * g.s, o2 = (double)(8 * kz) * g.s;
+    float hi[3], lo[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        double w = g.Rcw[3 * c + 0] * o0;
+        w = w + g.Rcw[3 * c + 1] * o1;
+        w = w + g.Rcw[3 * c + 2] * o2;
+        w = w + g.tcw[c];
+        hi[c] = (float)w;
+        lo[c] = (float)(w - (double)hi[c]);
+    }
+    const float mu = g.mu_f, inv_mu = 1.0f / mu;
+    const int64_t vbase = (int64_t)ptr * kBlockVox;
     uint32_t n_upd = 0;
-
-    for (int bi = __builtin_amdgcn_readfirstlane(blockIdx.x * waves_per_wg + wave_in_wg); bi < n_vis;
-         bi += gridDim.x * waves_per_wg) {
-        const int32_t e = a.vis_list[bi];
-        unsigned long long key;
-        int32_t ptr;
-        if (e < 2 * a.h.n_buckets) {
-            key = a.h.buckets[e >> 1].key[e & 1];
-            ptr = a.h.buckets[e >> 1].ptr[e & 1];
-        } else {
-            key = a.h.excess[e - 2 * a.h.n_buckets].key;
-            ptr = a.h.excess[e - 2 * a.h.n_buckets].ptr;
-        }
-        if (ptr < 0) continue;  // cannot happen: every flagged entry owns a block
-        int kx, ky, kz;
-        unpack_key(key, kx, ky, kz);
-        // block origin in camera coordinates, binary64 -> binary32 pair
-        const double o0 = (double)(8 * kx) * g.s, o1 = (double)(8 * ky) * g.s,
-                     o2 = (double)(8 * kz) * g.s;
-        float hi[3], lo[3];
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-            double w = g.Rcw[3 * c + 0] * o0;
-            w = w + g.Rcw[3 * c + 1] * o1;
-            w = w + g.Rcw[3 * c + 2] * o2;
-            w = w + g.tcw[c];
-            hi[c] = (float)w;
-            lo[c] = (float)(w - (double)hi[c]);
-        }
-        const int64_t vbase = (int64_t)ptr * kBlockVox;
+    for (int grp = 0; grp < 2; grp++) {
+        const int li0 = 4 * lane + 256 * grp;
+        const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
+        float eta[4];
+        uint32_t upd = 0;
 #pragma unroll
-        for (int grp = 0; grp < 2; grp++) {
-            const int li0 = 4 * lane + 256 * grp;
-            const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
-            float eta[4];
-            uint32_t upd = 0;
+        for (int j = 0; j < 4; j++) {
+            const float fx_ = (float)((li0 & 7) + j);
+            float p[3], dl2 = 0.0f;
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                float t = fx_ * g.g[0][c];
+                t = t + fy_ * g.g[1][c];
+                t = t + fz_ * g.g[2][c];
+                p[c] = hi[c] + (lo[c] + t);
+                if (c == 2) dl2 = t;
+            }
+            eta[j] = 0.0f;
+            if (p[2] <= 0.0f) continue;
+            const float x = g.fx * p[0] / p[2] + g.cx;
+            const float y = g.fy * p[1] / p[2] + g.cy;
+            if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
+            const float d = a.depth[(int)(x + 0.5f) + (int)(y + 0.5f) * g.W];
+            if (!(d > 0.0f) || isinf(d)) continue;
+            const float e32 = (d - hi[2]) - (lo[2] + dl2);
+            if (e32 < -mu) continue;
+            eta[j] = e32;
+            upd |= 1u << j;
+        }
+        if (upd) {
+            Group4<FMT> v;
+            v.load(a.sdf, a.w, vbase + li0);
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                const float fx_ = (float)((li0 & 7) + j);
-                float p[3], dl2 = 0.0f;
-#pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    float t = fx_ * g.g[0][c];
-                    t = t + fy_ * g.g[1][c];
-                    t = t + fz_ * g.g[2][c];
-                    p[c] = hi[c] + (lo[c] + t);
-                    if (c == 2) dl2 = t;
-                }
-                eta[j] = 0.0f;
-                if (p[2] <= 0.0f) continue;
-                const float x = g.fx * p[0] / p[2] + g.cx;
-                const float y = g.fy * p[1] / p[2] + g.cy;
-                if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
-                const float d = a.depth[(int)(x + 0.5f) + (int)(y + 0.5f) * g.W];
-                if (!(d > 0.0f) || isinf(d)) continue;
-                const float e32 = (d - hi[2]) - (lo[2] + dl2);
-                if (e32 < -mu) continue;
-                eta[j] = e32;
-                upd |= 1u << j;
+                if (!(upd & (1u << j))) continue;
+                const float f = fminf(1.0f, eta[j] * inv_mu);
+                const float F = v.F(j), W = v.Wv(j);
+                const float Wn = W + 1.0f;
+                // running average F <- (W F + f) / (W + 1), in incremental form
+                const float Fn = F + (f - F) / Wn;
+                v.set(j, Fn, fminf(Wn, g.max_w_f));
             }
-            if (upd) {
-                Group4<FMT> v;
-                v.load(a.sdf, a.w, vbase + li0);
-#pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    if (!(upd & (1u << j))) continue;
-                    const float f = fminf(1.0f, eta[j] * inv_mu);
-                    const float F = v.F(j), W = v.Wv(j);
-                    const float Wn = W + 1.0f;
-                    // running average F <- (W F + f) / (W + 1), in incremental form
-                    const float Fn = F + (f - F) / Wn;
-                    v.set(j, Fn, fminf(Wn, g.max_w_f));
-                }
-                v.store(a.sdf, a.w, vbase + li0);
-                n_upd += __builtin_popcount(upd);
-            }
+            v.store(a.sdf, a.w, vbase + li0);
+            n_upd += __builtin_popcount(upd);
         }
     }
+    return n_upd;
+}
+
+__device__ __forceinline__ int bytes_set(uint32_t x) { return (int)((x * 0x01010101u) >> 24); }
+
+constexpr int kScanThreads = 256;
+constexpr int kScanEntries = kScanThreads * 8;   // flag bytes per workgroup
+
+// Stage three of the allocation (the visible list) fused with the integration:
+// workgroup b scans flag bytes [2048 b, 2048 b + 2048), clears them, compacts
+// the set ones into an LDS list (wave prefix sums), and its 4 waves integrate
+// those blocks.  The hash spreads blocks uniformly over the entries, so every
+// workgroup gets about the same share (about 4 blocks at VGA).  The same pass
+// clears the allocation's claim-set slots.
+template <int FMT>
+__global__ __launch_bounds__(kScanThreads) void k_integrate(IntegrateArgs a)
+{
+    __shared__ int32_t s_list[kScanEntries];
+    __shared__ int s_wave[kScanThreads / kWave];
+    __shared__ int s_n, s_base;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int nwaves = kScanThreads / kWave;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt->set_used[a.parity ^ 1] = 0;  // next frame's counter
+    {
+        const int su = a.cnt->set_used[a.parity];
+        for (int i = blockIdx.x * kScanThreads + threadIdx.x; i < su; i += gridDim.x * kScanThreads)
+            a.set[a.set_list[i]] = 0ull;
+    }
+    // scan and clear 8 flags per thread
+    const int64_t w8 = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
+    uint2 f = make_uint2(0u, 0u);
+    if (w8 < a.n_words8) f = a.vis8[w8];
+    const int c = bytes_set(f.x) + bytes_set(f.y);
+    if (c) a.vis8[w8] = make_uint2(0u, 0u);
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    if (lane == kWave - 1) s_wave[wave] = incl;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < nwaves; w++) {
+            const int x = s_wave[w];
+            s_wave[w] = t;
+            t += x;
+        }
+        s_n = t;
+        if (t) {
+            const int sI = blockIdx.x % kStripes;
+            atomicAdd(&a.cnt->vis[0][sI][0], (unsigned long long)t);
+            atomicAdd(&a.cnt->vis[1][sI][0], (unsigned long long)t);
+            s_base = a.vis_list ? atomicAdd(&a.cnt->n_vis, t) : 0;
+        }
+    }
+    __syncthreads();
+    if (c) {
+        int k = s_wave[wave] + incl - c;
+        const uint32_t w2[2] = {f.x, f.y};
+#pragma unroll
+        for (int q = 0; q < 8; q++)
+            if ((w2[q >> 2] >> (8 * (q & 3))) & 0xffu) {
+                const int32_t e = (int32_t)(w8 * 8 + q);
+                s_list[k] = e;
+                if (a.vis_list) a.vis_list[s_base + k] = e;
+                k++;
+            }
+    }
+    __syncthreads();
+    const int n = s_n;
+    uint32_t n_upd = 0;
+    for (int j = wave; j < n; j += nwaves) n_upd += integrate_block<FMT>(a, s_list[j], lane);
     // one counter update per workgroup, on one of kStripes separate lines
-    __shared__ uint32_t wave_upd[256 / kWave];
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) n_upd += __shfl_xor(n_upd, o, kWave);
-    if (lane == 0) wave_upd[wave_in_wg] = n_upd;
+    __syncthreads();
+    if (lane == 0) s_wave[wave] = (int)n_upd;
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned long long t = 0;
-        for (int w = 0; w < waves_per_wg; w++) t += wave_upd[w];
+        for (int w = 0; w < nwaves; w++) t += (unsigned)s_wave[w];
         if (t) {
             const int sI = blockIdx.x % kStripes;
             atomicAdd(&a.cnt->upd[0][sI][0], t);
@@ -212,8 +271,9 @@ __global__ __launch_bounds__(256) void k_integrate(IntegrateArgs a)
     }
 }
 
-hipError_t launch_integrate(int fmt, const IntegrateArgs &a, int grid, hipStream_t st)
+hipError_t launch_integrate(int fmt, const IntegrateArgs &a, hipStream_t st)
 {
+    const int grid = (int)((a.n_words8 + kScanThreads - 1) / kScanThreads);
     switch (fmt) {
     case ITM_VOX_F32: k_integrate<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
     case ITM_VOX_F16: k_integrate<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;

@@ -7,7 +7,7 @@
 //            the paper keeps in the bucket's last entry
 //   excess   n_excess x 16 B    {key (u64), ptr (i32), next (i32)}  unordered part
 //   vis      n_entries bytes    per-entry visibility flag of the current frame
-//   vis_list n_entries x i32    compacted visible entry ids
+//   vis_list n_entries x i32    compacted visible entry ids (for the refiner gate)
 //   sdf, w   capacity x 512     voxel block array, structure of arrays, one
 //                               element type per storage form
 //   set      R x u64            per-frame set of blocks claimed for the excess list
@@ -46,19 +46,18 @@ struct alignas(16) Excess {
 static_assert(sizeof(Excess) == 16, "excess record is 16 bytes");
 
 struct Counters {
-    int32_t vba_next;     // voxel blocks handed out (bump allocator = free stack pop)
-    int32_t excess_next;  // excess entries handed out (may run past n_excess)
-    int32_t n_vis;        // visible entries of the current frame
-    int32_t set_used;     // claim-set slots used in the current frame
-    unsigned long long dropped_total;
-    int32_t n_vis_last;   // visible count of the last completed integration
+    int32_t vba_next;       // voxel blocks handed out (bump allocator = free stack pop)
+    int32_t excess_next;    // excess entries handed out (may run past n_excess)
+    int32_t n_vis;          // entries in the visible list (written only when a consumer needs it)
+    int32_t set_used[2];    // claim-set slots used, by frame parity
     int32_t pad;
-    unsigned long long vis_total;  // visible blocks summed over all integrations
-    unsigned long long pad2[4];
-    // updated-voxel counts, striped over separate 128-byte lines so that the
-    // per-workgroup additions do not all hit one address: [frame][stripe] for
-    // the current frame (cleared by k_alloc), [total][stripe] since creation
-    unsigned long long upd[2][kStripes][16];
+    unsigned long long dropped_total;
+    unsigned long long pad2[5];
+    // counts striped over separate 128-byte lines so that the per-workgroup
+    // additions do not all hit one address: [frame][stripe] for the current
+    // frame (cleared by k_alloc), [total][stripe] since creation
+    unsigned long long upd[2][kStripes][16];   // updated voxels
+    unsigned long long vis[2][kStripes][16];   // visible blocks
 };
 
 struct HashView {
@@ -67,6 +66,8 @@ struct HashView {
     uint32_t *occ;      // one bit per bucket: set once the bucket holds a block
     uint32_t *macro;    // kMacroBits bits, one per hashed macro cell (4^3 blocks): set
                         // once any block of a cell hashing there is allocated
+    uint32_t *bfilt;    // kBlockFilterBits bits, one per hashed block: set once a block
+                        // hashing there is allocated
     uint32_t mask;
     int32_t n_buckets;
     int32_t n_excess;
@@ -191,15 +192,7 @@ struct AllocArgs {
     unsigned long long *set;
     int32_t *set_list;
     uint32_t set_mask;
-    Counters *cnt;
-};
-
-struct CompactArgs {
-    uint4 *vis4;
-    int32_t n_chunks;
-    int32_t *vis_list;
-    unsigned long long *set;
-    const int32_t *set_list;
+    int32_t parity;         // frame parity: which claim counter to use
     Counters *cnt;
 };
 
@@ -207,11 +200,15 @@ struct IntegrateArgs {
     FrameGeom fg;
     const float *depth;
     HashView h;
-    const int32_t *vis_list;
+    uint2 *vis8;              // visibility flags, 8 entries per word (cleared here)
+    int64_t n_words8;
+    unsigned long long *set;  // claim set of the allocation (cleared here)
+    const int32_t *set_list;
+    int32_t parity;           // frame parity: which claim counter this frame used
+    int32_t *vis_list;        // written when non-null (a later kernel consumes it)
     void *sdf;
     void *w;
     Counters *cnt;
-    int32_t *host_hint;   // mapped pinned host word: visible count (may be null)
 };
 
 struct RaycastArgs {
@@ -269,8 +266,7 @@ hipError_t launch_refine_gather(int fmt, const HashView &h, const void *sdf, con
 
 // launchers (one translation unit each)
 hipError_t launch_alloc(const AllocArgs &a, hipStream_t st);
-hipError_t launch_compact(const CompactArgs &a, int grid, hipStream_t st);
-hipError_t launch_integrate(int fmt, const IntegrateArgs &a, int grid, hipStream_t st);
+hipError_t launch_integrate(int fmt, const IntegrateArgs &a, hipStream_t st);
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st);
 hipError_t launch_init(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_t *vis, int64_t nvis,
                        unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
@@ -294,13 +290,22 @@ __device__ __forceinline__ bool xcd_tile(int n_tx, int n_ty, int &tx, int &ty)
 }
 __host__ __forceinline__ int xcd_grid(int n_tiles) { return (n_tiles + kXcds - 1) / kXcds * kXcds; }
 
-constexpr int kMacroShift = 2;         // macro cell = 4 x 4 x 4 blocks
-constexpr int kMacroBits = 1 << 17;    // 16 KiB: small enough to sit in LDS
+// Two small hashed occupancy filters, staged in LDS by the raycast: no false
+// negatives, so a clear bit proves a block (or a whole macro cell) absent.
+constexpr int kMacroShift = 2;              // macro cell = 4 x 4 x 4 blocks
+constexpr int kMacroBits = 1 << 16;         // 8 KiB
 constexpr int kMacroWords = kMacroBits / 32;
+constexpr int kBlockFilterBits = 1 << 17;   // 16 KiB
+constexpr int kBlockFilterWords = kBlockFilterBits / 32;
 
 __device__ __forceinline__ uint32_t macro_index(int bx, int by, int bz)
 {
     return hash_index(bx >> kMacroShift, by >> kMacroShift, bz >> kMacroShift, kMacroBits - 1);
+}
+__device__ __forceinline__ uint32_t bfilt_index(int bx, int by, int bz)
+{
+    // a different mix from hashIndex, so that filter and bucket collisions are independent
+    return ((uint32_t)bx * 2654435761u ^ (uint32_t)by * 2246822519u ^ (uint32_t)bz * 3266489917u) >> 15;
 }
 
 // retrieval without the bucket bitmap, for blocks that are probably allocated

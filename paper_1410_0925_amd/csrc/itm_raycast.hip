@@ -26,17 +26,19 @@ template <int FMT>
 struct BlockReader {
     const HashView &h;
     const typename Vox<FMT>::S *sdf;
+    const uint32_t *filt;   // block filter in LDS
     int cx, cy, cz;
     int32_t cptr;
 
-    __device__ BlockReader(const HashView &hv, const void *s)
-        : h(hv), sdf((const typename Vox<FMT>::S *)s), cx(INT_MIN), cy(0), cz(0), cptr(-1) {}
+    __device__ BlockReader(const HashView &hv, const void *s, const uint32_t *f)
+        : h(hv), sdf((const typename Vox<FMT>::S *)s), filt(f), cx(INT_MIN), cy(0), cz(0), cptr(-1) {}
 
     __device__ int32_t block(int bx, int by, int bz)
     {
         if (bx != cx || by != cy || bz != cz) {
             cx = bx; cy = by; cz = bz;
-            cptr = find_block(h, bx, by, bz);
+            const uint32_t fi = bfilt_index(bx, by, bz);
+            cptr = ((filt[fi >> 5] >> (fi & 31)) & 1u) ? find_block_direct(h, bx, by, bz) : -1;
         }
         return cptr;
     }
@@ -59,8 +61,8 @@ struct Cube {
     int bx0, by0, bz0;
     int32_t p[8];   // block pointer of (dx, dy, dz) = (c & 1, c >> 1 & 1, c >> 2 & 1)
 
-    // blocks near a surface are almost always allocated, so they are probed
-    // directly; the march's cached block is reused without a probe
+    // the march's cached block is reused; others are probed unless the LDS block
+    // filter proves them absent
     __device__ void fetch(const HashView &h, const BlockReader<FMT> &rd, int lx, int ly, int lz, int hx,
                           int hy, int hz)
     {
@@ -73,7 +75,9 @@ struct Cube {
             const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
             const int kx = dx ? bx1 : bx0, ky = dy ? by1 : by0, kz = dz ? bz1 : bz0;
             const bool cached = kx == rd.cx && ky == rd.cy && kz == rd.cz;
-            p[c] = !need ? -1 : cached ? rd.cptr : find_block_direct(h, kx, ky, kz);
+            const uint32_t fi = bfilt_index(kx, ky, kz);
+            const bool maybe = (rd.filt[fi >> 5] >> (fi & 31)) & 1u;
+            p[c] = !need ? -1 : cached ? rd.cptr : maybe ? find_block_direct(h, kx, ky, kz) : -1;
         }
     }
     __device__ float F(const typename Vox<FMT>::S *sdf, int vx, int vy, int vz) const
@@ -86,30 +90,37 @@ struct Cube {
         if (ptr < 0) return 1.0f;
         return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7)]);
     }
-    // trilinear interpolation at q with i = floor(q) inside the region
-    __device__ float trilinear(const typename Vox<FMT>::S *sdf, int ix, int iy, int iz, float rx,
-                               float ry, float rz) const
+    // the 8 lattice voxels of the cell with corner i
+    __device__ void cell(const typename Vox<FMT>::S *sdf, int ix, int iy, int iz, float Fc[8]) const
     {
-        float acc = 0.0f;
 #pragma unroll
-        for (int c = 0; c < 8; c++) {
-            const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
-            const float w = (dx ? rx : 1.0f - rx) * (dy ? ry : 1.0f - ry) * (dz ? rz : 1.0f - rz);
-            acc = fmaf(w, F(sdf, ix + dx, iy + dy, iz + dz), acc);
-        }
-        return acc;
+        for (int c = 0; c < 8; c++) Fc[c] = F(sdf, ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1));
     }
 };
 
+__device__ __forceinline__ float trilinear8(const float Fc[8], float rx, float ry, float rz)
+{
+    float acc = 0.0f;
+#pragma unroll
+    for (int c = 0; c < 8; c++) {
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        const float w = (dx ? rx : 1.0f - rx) * (dy ? ry : 1.0f - ry) * (dz ? rz : 1.0f - rz);
+        acc = fmaf(w, Fc[c], acc);
+    }
+    return acc;
+}
+
+// the 8 voxels of the cell of q (with the cell corner and fractions)
 template <int FMT>
-__device__ float trilinear_at(const HashView &h, const BlockReader<FMT> &rd,
-                              const typename Vox<FMT>::S *sdf, float qx, float qy, float qz)
+__device__ void cell_at(const HashView &h, const BlockReader<FMT> &rd, const typename Vox<FMT>::S *sdf,
+                        float qx, float qy, float qz, int i[3], float r[3], float Fc[8])
 {
     const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-    const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
+    i[0] = (int)fx; i[1] = (int)fy; i[2] = (int)fz;
+    r[0] = qx - fx; r[1] = qy - fy; r[2] = qz - fz;
     Cube<FMT> cb;
-    cb.fetch(h, rd, ix, iy, iz, ix + 1, iy + 1, iz + 1);
-    return cb.trilinear(sdf, ix, iy, iz, qx - fx, qy - fy, qz - fz);
+    cb.fetch(h, rd, i[0], i[1], i[2], i[0] + 1, i[1] + 1, i[2] + 1);
+    cb.cell(sdf, i[0], i[1], i[2], Fc);
 }
 
 template <int FMT>
@@ -118,14 +129,16 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     const FrameGeom &g = a.fg;
     int tx, ty;
     if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;  // whole workgroup
-    // the macro-cell bitmap, staged in LDS: empty-space tests cost an LDS read
-    __shared__ uint32_t s_macro[kMacroWords];
+    // the macro-cell and block filters, staged in LDS: empty-space tests cost an
+    // LDS read (they are contiguous in global memory)
+    __shared__ uint32_t s_filt[kMacroWords + kBlockFilterWords];
     {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.h.macro);
-        uint4 *dst = reinterpret_cast<uint4 *>(s_macro);
-        for (int i = threadIdx.x; i < kMacroWords / 4; i += blockDim.x) dst[i] = src[i];
+        uint4 *dst = reinterpret_cast<uint4 *>(s_filt);
+        for (int i = threadIdx.x; i < (kMacroWords + kBlockFilterWords) / 4; i += blockDim.x) dst[i] = src[i];
     }
     __syncthreads();
+    const uint32_t *s_macro = s_filt;
     // a workgroup covers 16 x 16 pixels, each wave an 8 x 8 quadrant of it
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int u = tx * 16 + (wave & 1) * 8 + (lane & 7);
@@ -148,7 +161,7 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     // reciprocal direction for the macro-cell exit
     const float idx = 1.0f / dx, idy = 1.0f / dy, idz = 1.0f / dz;
 
-    BlockReader<FMT> rd(a.h, a.sdf);
+    BlockReader<FMT> rd(a.h, a.sdf, s_filt + kMacroWords);
     float t = t_near;
     int state = RC_COARSE, fine_miss = 0;
     for (int it = 0; it < cap && t < t_far; it++) {
@@ -202,21 +215,54 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     float4 P = make_float4(0.f, 0.f, 0.f, 0.f), N = make_float4(0.f, 0.f, 0.f, 0.f);
     if (state == RC_BEHIND) {
         const auto *sdf = (const typename Vox<FMT>::S *)a.sdf;
+        int ci[3];
+        float cr[3], Fc[8];
 #pragma unroll
-        for (int k = 0; k < 2; k++)
-            t = fmaf(trilinear_at<FMT>(a.h, rd, sdf, fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz)), mu, t);
+        for (int k = 0; k < 2; k++) {
+            cell_at<FMT>(a.h, rd, sdf, fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz), ci, cr, Fc);
+            t = fmaf(trilinear8(Fc, cr[0], cr[1], cr[2]), mu, t);
+        }
         const float qx = fmaf(t, dx, ox), qy = fmaf(t, dy, oy), qz = fmaf(t, dz, oz);
         P = make_float4((float)(g.twc[0] + (double)t * dir[0]), (float)(g.twc[1] + (double)t * dir[1]),
                         (float)(g.twc[2] + (double)t * dir[2]), 1.0f);
-        // the six samples q +- e_a read voxels floor(q) - 1 .. floor(q) + 2
+        // normal: central differences of F_t at q +- one voxel per axis.  They read
+        // the cell of q (usually the second refinement's cell, already loaded) and
+        // its 6 face neighbours' outer layers, 24 more voxels in one batch.
         const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
         const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
         const float rx = qx - fx, ry = qy - fy, rz = qz - fz;
         Cube<FMT> cb;
         cb.fetch(a.h, rd, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
-        const float gx = cb.trilinear(sdf, ix + 1, iy, iz, rx, ry, rz) - cb.trilinear(sdf, ix - 1, iy, iz, rx, ry, rz);
-        const float gy = cb.trilinear(sdf, ix, iy + 1, iz, rx, ry, rz) - cb.trilinear(sdf, ix, iy - 1, iz, rx, ry, rz);
-        const float gz = cb.trilinear(sdf, ix, iy, iz + 1, rx, ry, rz) - cb.trilinear(sdf, ix, iy, iz - 1, rx, ry, rz);
+        if (ix != ci[0] || iy != ci[1] || iz != ci[2]) cb.cell(sdf, ix, iy, iz, Fc);
+        float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int a0 = k & 1, a1 = k >> 1;
+            Ex[0][k] = cb.F(sdf, ix - 1, iy + a0, iz + a1);
+            Ex[1][k] = cb.F(sdf, ix + 2, iy + a0, iz + a1);
+            Ey[0][k] = cb.F(sdf, ix + a0, iy - 1, iz + a1);
+            Ey[1][k] = cb.F(sdf, ix + a0, iy + 2, iz + a1);
+            Ez[0][k] = cb.F(sdf, ix + a0, iy + a1, iz - 1);
+            Ez[1][k] = cb.F(sdf, ix + a0, iy + a1, iz + 2);
+        }
+        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const int a0 = k & 1, a1 = k >> 1;
+            // x pair: corners (y, z) = (iy + a0, iz + a1); Fc index dx + 2 dy + 4 dz
+            const float wyz = (a0 ? ry : 1.0f - ry) * (a1 ? rz : 1.0f - rz);
+            const float xp = (1.0f - rx) * Fc[1 + 2 * a0 + 4 * a1] + rx * Ex[1][k];
+            const float xm = (1.0f - rx) * Ex[0][k] + rx * Fc[0 + 2 * a0 + 4 * a1];
+            gx = fmaf(wyz, xp - xm, gx);
+            const float wxz = (a0 ? rx : 1.0f - rx) * (a1 ? rz : 1.0f - rz);
+            const float yp = (1.0f - ry) * Fc[a0 + 2 + 4 * a1] + ry * Ey[1][k];
+            const float ym = (1.0f - ry) * Ey[0][k] + ry * Fc[a0 + 0 + 4 * a1];
+            gy = fmaf(wxz, yp - ym, gy);
+            const float wxy = (a0 ? rx : 1.0f - rx) * (a1 ? ry : 1.0f - ry);
+            const float zp = (1.0f - rz) * Fc[a0 + 2 * a1 + 4] + rz * Ez[1][k];
+            const float zm = (1.0f - rz) * Ez[0][k] + rz * Fc[a0 + 2 * a1 + 0];
+            gz = fmaf(wxy, zp - zm, gz);
+        }
         const float n2 = gx * gx + gy * gy + gz * gz;
         if (n2 > 0.0f) {
             const float r = 1.0f / sqrtf(n2);

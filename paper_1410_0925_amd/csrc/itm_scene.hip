@@ -80,8 +80,6 @@ struct itm_scene {
     Counters *cnt = nullptr;
     uint32_t *occ = nullptr;
     int64_t occ_words = 0;
-    int32_t *hint_host = nullptr;  // mapped pinned word written by k_compact
-    int32_t *hint_dev = nullptr;
 
     itm_refiner *refiner = nullptr;   // not owned
     float refine_w_threshold = 0.0f;
@@ -119,7 +117,6 @@ void release(itm_scene *sc)
     (void)hipFree(sc->occ);
     (void)hipFree(sc->refined);
     (void)hipFree(sc->stamp);
-    if (sc->hint_host) (void)hipHostFree(sc->hint_host);
     delete sc;
 }
 
@@ -185,6 +182,7 @@ HashView hash_view(const itm_scene *sc)
     h.excess = sc->excess;
     h.occ = sc->occ;
     h.macro = sc->occ + sc->occ_words;
+    h.bfilt = h.macro + kMacroWords;
     h.mask = sc->mask;
     h.n_buckets = (int32_t)sc->n_buckets;
     h.n_excess = (int32_t)sc->n_excess;
@@ -301,22 +299,15 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
         dev_alloc((void **)&sc->set, sizeof(unsigned long long) * sc->set_size, "claim set") ||
         dev_alloc((void **)&sc->set_list, sizeof(int32_t) * sc->set_size, "claim list") ||
         dev_alloc((void **)&sc->cnt, sizeof(Counters), "counters") ||
-        dev_alloc((void **)&sc->occ, sizeof(uint32_t) * ((n_buckets + 31) / 32 + kMacroWords),
+        dev_alloc((void **)&sc->occ,
+                  sizeof(uint32_t) * ((n_buckets + 31) / 32 + kMacroWords + kBlockFilterWords),
                   "occupancy bitmaps")) {
         release(sc);
         return nullptr;
     }
-    if (hipHostMalloc((void **)&sc->hint_host, sizeof(int32_t), hipHostMallocMapped) != hipSuccess ||
-        hipHostGetDevicePointer((void **)&sc->hint_dev, sc->hint_host, 0) != hipSuccess) {
-        (void)hipGetLastError();
-        sc->hint_host = nullptr;
-        sc->hint_dev = nullptr;
-    } else {
-        *sc->hint_host = 0;
-    }
     sc->occ_words = (n_buckets + 31) / 32;
     hipError_t e = launch_init(sc->buckets, n_buckets, sc->excess, n_excess, sc->vis, sc->vis_bytes,
-                               sc->set, sc->set_size, sc->occ, sc->occ_words + kMacroWords,
+                               sc->set, sc->set_size, sc->occ, sc->occ_words + kMacroWords + kBlockFilterWords,
                                sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     if (e != hipSuccess) {
@@ -349,6 +340,7 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
     FrameGeom g;
     if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
     const HashView h = hash_view(sc);
+    const int32_t parity = sc->frame & 1;
     {
         ProfScope ps(sc, 0);
         AllocArgs a;
@@ -359,38 +351,26 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
         a.set = sc->set;
         a.set_list = sc->set_list;
         a.set_mask = (uint32_t)(sc->set_size - 1);
+        a.parity = parity;
         a.cnt = sc->cnt;
         HIP_TRY(launch_alloc(a, sc->stream));
     }
     {
         ProfScope ps(sc, 1);
-        CompactArgs c;
-        c.vis4 = reinterpret_cast<uint4 *>(sc->vis);
-        c.n_chunks = (int32_t)(sc->vis_bytes / 16);
-        c.vis_list = sc->vis_list;
-        c.set = sc->set;
-        c.set_list = sc->set_list;
-        c.cnt = sc->cnt;
-        const int grid = (int)std::min<int64_t>((c.n_chunks + 1023) / 1024, (int64_t)sc->num_cu * 8);
-        HIP_TRY(launch_compact(c, std::max(grid, 1), sc->stream));
-    }
-    {
-        ProfScope ps(sc, 2);
         IntegrateArgs ia;
         ia.fg = g;
         ia.depth = depth;
         ia.h = h;
-        ia.vis_list = sc->vis_list;
+        ia.vis8 = reinterpret_cast<uint2 *>(sc->vis);
+        ia.n_words8 = sc->vis_bytes / 8;
+        ia.set = sc->set;
+        ia.set_list = sc->set_list;
+        ia.parity = parity;
+        ia.vis_list = sc->refiner ? sc->vis_list : nullptr;   // the refiner gate reads the list
         ia.sdf = sc->sdf;
         ia.w = sc->w;
         ia.cnt = sc->cnt;
-        ia.host_hint = sc->hint_dev;
-        // grid-stride over the device-side count; the size follows the last known
-        // visible count (4 blocks per workgroup), at least one workgroup per CU
-        int64_t last = sc->hint_host ? *(volatile int32_t *)sc->hint_host : 0;
-        int64_t grid = std::max<int64_t>((last + last / 4 + 3) / 4, (int64_t)sc->num_cu * 2);
-        grid = std::min<int64_t>(grid, (int64_t)sc->num_cu * 64);
-        HIP_TRY(launch_integrate(sc->fmt, ia, (int)grid, sc->stream));
+        HIP_TRY(launch_integrate(sc->fmt, ia, sc->stream));
     }
     sc->frame++;
     if (sc->refiner) {
@@ -408,6 +388,7 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
         ra.refined = sc->refined;
         ra.stamp = sc->stamp;
         ra.frame = sc->frame;
+        ProfScope ps(sc, 3);
         HIP_TRY(launch_refine_gated(sc->fmt, ra, sc->num_cu * 2, sc->stream));
     }
     return ITM_OK;
@@ -421,7 +402,7 @@ itm_status itm_raycast(itm_scene *sc, const itm_intrinsics *K, const double *T_w
         return fail(ITM_ERR_ARG, "outputs must be 16-byte aligned");
     FrameGeom g;
     if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
-    ProfScope ps(sc, 3);
+    ProfScope ps(sc, 2);
     RaycastArgs a;
     a.fg = g;
     a.h = hash_view(sc);
@@ -439,7 +420,12 @@ itm_status itm_get_stats(itm_scene *sc, itm_stats *out)
     HIP_TRY(hipMemcpyAsync(&c, sc->cnt, sizeof c, hipMemcpyDeviceToHost, sc->stream));
     HIP_TRY(hipStreamSynchronize(sc->stream));
     out->n_allocated = std::min<int64_t>(c.vba_next, sc->vba_cap);
-    out->n_visible_last = c.n_vis_last;
+    unsigned long long v_last = 0, v_tot = 0;
+    for (int i = 0; i < kStripes; i++) {
+        v_last += c.vis[0][i][0];
+        v_tot += c.vis[1][i][0];
+    }
+    out->n_visible_last = (int64_t)v_last;
     out->n_excess_used = std::min<int64_t>(c.excess_next, sc->n_excess);
     out->n_dropped_total = (int64_t)c.dropped_total;
     out->vba_capacity = sc->vba_cap;
@@ -451,7 +437,7 @@ itm_status itm_get_stats(itm_scene *sc, itm_stats *out)
     out->n_updated_last = (int64_t)u_last;
     out->n_entries = sc->n_entries;
     out->bytes_per_voxel = (int64_t)(sdf_elem(sc->fmt) + w_elem(sc->fmt));
-    out->n_visible_total = (int64_t)c.vis_total;
+    out->n_visible_total = (int64_t)v_tot;
     out->n_updated_total = (int64_t)u_tot;
     return ITM_OK;
 }
