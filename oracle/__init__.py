@@ -67,7 +67,9 @@ def lib():
             "orc_dense_integrate": (_i64, [_P, _P, C.c_int, C.c_int, _P, _P, _P, _i64]),
             "orc_dense_read": (None, [_P, _P, _P, _P]),
             "orc_raycast": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P]),
+            "orc_raycast_range": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
             "orc_raycast_crossing": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
+            "orc_expected_depths": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
             "orc_num_threads": (C.c_int, []),
         }
         for name, (res, args) in sig.items():
@@ -189,16 +191,28 @@ class Scene:
                                            _ptr(np.ascontiguousarray(T_wc, np.float64)),
                                            _ptr(vox), _ptr(act), len(vox), _ptr(F), _ptr(Wt)))
 
-    def raycast(self, W, H, intr, T_wc):
-        """Returns (pts [H,W,4], normals [H,W,4], camera depth [H,W], flags, steps)."""
+    def raycast(self, W, H, intr, T_wc, zrange=None):
+        """Returns (pts [H,W,4], normals [H,W,4], camera depth [H,W], flags, steps).
+        zrange: [H,W,2] binary32 expected depth ranges (expected_depths), or None
+        for the fixed range [z_near, z_far]."""
         pts = np.empty((H, W, 4), np.float64)
         nrm = np.empty((H, W, 4), np.float64)
         zc = np.empty((H, W), np.float64)
         fl = np.empty((H, W), np.uint8)
         st = np.empty((H, W), np.int32)
-        lib().orc_raycast(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
-                          _ptr(pts), _ptr(nrm), _ptr(zc), _ptr(fl), _ptr(st))
+        zr = None if zrange is None else np.ascontiguousarray(zrange, np.float32)
+        assert zr is None or zr.shape == (H, W, 2)
+        lib().orc_raycast_range(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                                _ptr(zr), _ptr(pts), _ptr(nrm), _ptr(zc), _ptr(fl), _ptr(st))
         return pts, nrm, zc, fl, st
+
+    def expected_depths(self, W, H, intr, T_wc):
+        """[H,W,2] binary32 (z_min, z_max) per pixel from the last frame's visible
+        blocks; (+inf, 0) where no block projects."""
+        zr = np.empty((H, W, 2), np.float32)
+        lib().orc_expected_depths(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                                  _ptr(zr))
+        return zr
 
     def raycast_crossing(self, W, H, intr, T_wc):
         zc = np.empty((H, W), np.float64)

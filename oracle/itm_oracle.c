@@ -26,6 +26,8 @@
  *                                          (computeUpdatedVoxelDepthInfo)
  *   dense volume ......................... section "Dense Volumes"
  *   raycast state machine ................ section "Raycast"
+ *   expected depth range per pixel ....... section "Raycast" (search range,
+ *                                          CreateExpectedDepths)
  * Readings where the paper is silent are noted beside the code that takes them.
  */
 #include <math.h>
@@ -819,7 +821,12 @@ typedef struct {
     double o[3], d[3], t_near, t_far, len;
 } orc_ray;
 
-static void orc_ray_setup(const orc_scene *sc, const orc_cam *c, int u, int v, orc_ray *r)
+/* zr: this pixel's expected depth range (camera depth, zr[0] = min, zr[1] = max)
+ * or NULL for the fixed range [z_near, z_far].  With a range the ray searches
+ * t in [max(z_min len, t_near), min(z_max len, t_far)]; an empty range (no
+ * visible block projects onto the pixel) leaves nothing to search. */
+static void orc_ray_setup(const orc_scene *sc, const orc_cam *c, int u, int v, const float *zr,
+                          orc_ray *r)
 {
     double cd[3] = {((double)u - c->cx) / c->fx, ((double)v - c->cy) / c->fy, 1.0};
     r->len = sqrt(cd[0] * cd[0] + cd[1] * cd[1] + 1.0);
@@ -829,6 +836,12 @@ static void orc_ray_setup(const orc_scene *sc, const orc_cam *c, int u, int v, o
     }
     r->t_near = (double)sc->z_near * r->len;
     r->t_far = (double)sc->z_far * r->len;
+    if (zr) {
+        if (!((double)zr[0] <= (double)zr[1])) { r->t_far = r->t_near; return; }
+        double a = (double)zr[0] * r->len, b = (double)zr[1] * r->len;
+        if (a > r->t_near) r->t_near = a;
+        if (b < r->t_far) r->t_far = b;
+    }
 }
 
 /* flags bit 0: a sign decision had |F_n| < 1e-4; bit 1: iteration cap reached */
@@ -884,9 +897,11 @@ static int orc_march(const orc_scene *sc, const orc_ray *r, double *t_hit, int *
 
 /* pts/normals: H*W*4 binary64, world frame; pts w = 1 on a hit, all zero on a
  * miss; normals w = 1 when the gradient is non-zero.  zc: camera depth of the
- * hit (0 on a miss).  flags/steps per pixel may be NULL. */
-int orc_raycast(const orc_scene *sc, int W, int H, const double *K, const double *T_wc,
-                double *pts, double *normals, double *zc, uint8_t *flags, int32_t *steps)
+ * hit (0 on a miss).  flags/steps per pixel may be NULL.  zr: H*W*2 expected
+ * depth ranges (see orc_expected_depths) or NULL for [z_near, z_far]. */
+int orc_raycast_range(const orc_scene *sc, int W, int H, const double *K, const double *T_wc,
+                      const float *zr, double *pts, double *normals, double *zc, uint8_t *flags,
+                      int32_t *steps)
 {
     orc_cam c;
     orc_cam_setup(&c, W, H, K, T_wc);
@@ -895,7 +910,7 @@ int orc_raycast(const orc_scene *sc, int W, int H, const double *K, const double
         for (int u = 0; u < W; u++) {
             int64_t i = (int64_t)v * W + u;
             orc_ray r;
-            orc_ray_setup(sc, &c, u, v, &r);
+            orc_ray_setup(sc, &c, u, v, zr ? zr + 2 * i : NULL, &r);
             double t = 0;
             int fl = 0, st = 0;
             int hit = orc_march(sc, &r, &t, &fl, &st);
@@ -925,6 +940,12 @@ int orc_raycast(const orc_scene *sc, int W, int H, const double *K, const double
     return 0;
 }
 
+int orc_raycast(const orc_scene *sc, int W, int H, const double *K, const double *T_wc,
+                double *pts, double *normals, double *zc, uint8_t *flags, int32_t *steps)
+{
+    return orc_raycast_range(sc, W, H, K, T_wc, NULL, pts, normals, zc, flags, steps);
+}
+
 /* plain-definition cross-check of the raycast: the first + to - zero crossing
  * of F_t along the ray over [t_near, t_far], sampled every s / 4 and bisected
  * to 1e-7 m.  zc: camera depth of the crossing, 0 when there is none. */
@@ -937,7 +958,7 @@ int orc_raycast_crossing(const orc_scene *sc, int W, int H, const double *K, con
     for (int v = 0; v < H; v++) {
         for (int u = 0; u < W; u++) {
             orc_ray r;
-            orc_ray_setup(sc, &c, u, v, &r);
+            orc_ray_setup(sc, &c, u, v, NULL, &r);
             double h = sc->s / 4.0, t0 = r.t_near;
             double p[3] = {r.o[0] + t0 * r.d[0], r.o[1] + t0 * r.d[1], r.o[2] + t0 * r.d[2]};
             double f0 = orc_read_trilinear(sc, p), res = 0;
@@ -959,6 +980,97 @@ int orc_raycast_crossing(const orc_scene *sc, int W, int H, const double *K, con
             }
             zc[(int64_t)v * W + u] = res;
         }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Expected depth range per pixel (section "Raycast", the search range):      */
+/* every block visible in the last frame is projected into the image; the     */
+/* pixels inside the 2D bounding box of its projection get the minimum and     */
+/* maximum camera depth of its 3D bounding box, overlapping boxes combined by  */
+/* min and max.  Readings:                                                      */
+/*   - a block's 3D box is the region whose samples read it in the march       */
+/*     (nearest voxel): [8k - 1/2, 8k + 7 1/2] s per axis, so every sample that */
+/*     finds the block lies inside the box;                                    */
+/*   - the 2D box is that of the 8 projected corners; pixel (u, v), centre at  */
+/*     integer coordinates, is inside when ceil(x_min) <= u <= floor(x_max),   */
+/*     likewise v, clipped to the image;                                       */
+/*   - a block with a corner at camera depth <= 0 cannot be projected: it      */
+/*     covers the whole image with the range [0, its largest corner depth];    */
+/*   - arithmetic in binary64, corners as ((R0 X0 + R1 X1) + R2 X2) + t, the   */
+/*     range stored in binary32 rounded outwards (min down, max up);           */
+/*   - a pixel no block covers gets the empty range (+inf, 0).                 */
+/* zr: H*W*2 binary32, (z_min, z_max) per pixel.                               */
+/* ------------------------------------------------------------------------- */
+static float orc_round_down(double z)
+{
+    float f = (float)z;
+    if ((double)f > z) f = nextafterf(f, -INFINITY);
+    return f;
+}
+
+static float orc_round_up(double z)
+{
+    float f = (float)z;
+    if ((double)f < z) f = nextafterf(f, INFINITY);
+    return f;
+}
+
+int orc_expected_depths(const orc_scene *sc, int W, int H, const double *K, const double *T_wc,
+                        float *zr)
+{
+    orc_cam c;
+    orc_cam_setup(&c, W, H, K, T_wc);
+    for (int64_t i = 0; i < (int64_t)W * H; i++) { zr[2 * i] = INFINITY; zr[2 * i + 1] = 0.0f; }
+    for (int64_t e = 0; e < sc->n_entries; e++) {
+        if (!sc->vis[e]) continue;
+        const int32_t k[3] = {sc->e[e].x, sc->e[e].y, sc->e[e].z};
+        double zlo = INFINITY, zhi = -INFINITY, xlo = INFINITY, xhi = -INFINITY;
+        double ylo = INFINITY, yhi = -INFINITY;
+        int behind = 0;
+        for (int corner = 0; corner < 8; corner++) {
+            double X[3], P[3];
+            for (int a = 0; a < 3; a++) {
+                int up = (corner >> a) & 1;
+                X[a] = ((double)(8 * k[a]) - 0.5 + (up ? 8.0 : 0.0)) * sc->s;
+            }
+            for (int a = 0; a < 3; a++) {
+                double w = c.Rcw[3 * a + 0] * X[0];
+                w = w + c.Rcw[3 * a + 1] * X[1];
+                w = w + c.Rcw[3 * a + 2] * X[2];
+                P[a] = w + c.tcw[a];
+            }
+            if (P[2] < zlo) zlo = P[2];
+            if (P[2] > zhi) zhi = P[2];
+            if (P[2] <= 0.0) { behind = 1; continue; }
+            double x = c.fx * P[0] / P[2] + c.cx, y = c.fy * P[1] / P[2] + c.cy;
+            if (x < xlo) xlo = x;
+            if (x > xhi) xhi = x;
+            if (y < ylo) ylo = y;
+            if (y > yhi) yhi = y;
+        }
+        int u0, u1, v0, v1;
+        if (behind) {
+            u0 = 0; u1 = W - 1; v0 = 0; v1 = H - 1;
+            zlo = 0.0;
+        } else {
+            double a0 = ceil(xlo), a1 = floor(xhi), b0 = ceil(ylo), b1 = floor(yhi);
+            if (a1 < 0.0 || b1 < 0.0 || a0 > (double)(W - 1) || b0 > (double)(H - 1) || a0 > a1 ||
+                b0 > b1)
+                continue;
+            u0 = a0 < 0.0 ? 0 : (int)a0;
+            v0 = b0 < 0.0 ? 0 : (int)b0;
+            u1 = a1 > (double)(W - 1) ? W - 1 : (int)a1;
+            v1 = b1 > (double)(H - 1) ? H - 1 : (int)b1;
+        }
+        float fz0 = orc_round_down(zlo), fz1 = orc_round_up(zhi);
+        for (int v = v0; v <= v1; v++)
+            for (int u = u0; u <= u1; u++) {
+                float *r = zr + 2 * ((int64_t)v * W + u);
+                if (fz0 < r[0]) r[0] = fz0;
+                if (fz1 > r[1]) r[1] = fz1;
+            }
     }
     return 0;
 }
