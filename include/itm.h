@@ -125,9 +125,39 @@ itm_status itm_integrate(itm_scene *scene, const float *depth, const itm_intrins
  *   vanishes); a miss gets all zeros in both.
  * The search covers camera depths [z_near, z_far] with the state machine of the
  * paper (coarse block steps, fine steps of mu, steps of the TSDF value, two
- * trilinear refinement steps behind the surface).  Asynchronous. */
+ * trilinear refinement steps behind the surface) -- narrowed, when the search
+ * range is on (itm_scene_set_search_range), to the pixel's expected depth range
+ * from the last frame's visible blocks (itm_expected_depths); a pixel no visible
+ * block projects onto is then a miss.  Asynchronous. */
 itm_status itm_raycast(itm_scene *scene, const itm_intrinsics *K, const double *T_wc,
                        float *out_pts, float *out_normals);
+
+/* Search range of the raycast (section "Raycast": the visible blocks of the last
+ * frame, forward-projected, give each pixel the minimum and maximum depth to
+ * expect).  enable != 0 turns it on for later itm_raycast calls; while it is on,
+ * itm_integrate also bins the rectangles at the frame's own pose, which a
+ * raycast at exactly that pose (same K and T_wc bits) then reuses; any other
+ * pose bins them again from the visible list.
+ *   tile_capacity  rectangles kept per 16 x 16 pixel tile (<= 0: 512, at most
+ *                  65536).  A tile with more is still exact: its workgroup then
+ *                  recomputes every visible block (slow).
+ * Results with the range on are those of the paper's raycast with a search
+ * range; with it off (the default) every pixel searches [z_near, z_far].
+ * Synchronises the scene's stream when the capacity changes. */
+itm_status itm_scene_set_search_range(itm_scene *scene, int32_t enable, int32_t tile_capacity);
+
+/* The expected depth range image (section "Raycast", CreateExpectedDepths) at
+ * pose T_wc, from the visible blocks of the last itm_integrate:
+ *   zrange  DEVICE pointer, K->height * K->width float2 (8-byte aligned),
+ *           row-major: (z_min, z_max) in camera depth, metres.
+ * Each visible block's box [8k - 1/2, 8k + 7 1/2] s (per axis, the region whose
+ * samples read the block) is projected; the pixels whose centres lie in the 2D
+ * bounding box of its 8 corners (clipped to the image) get the min / max of the
+ * corners' camera depths (binary64, rounded outwards to binary32), combined over
+ * blocks by min / max.  A block with a corner at camera depth <= 0 covers the
+ * whole image from depth 0.  Pixels no block covers get (+inf, 0).
+ * Works whether or not the search range is on.  Asynchronous. */
+itm_status itm_expected_depths(itm_scene *scene, const itm_intrinsics *K, const double *T_wc, float *zrange);
 
 /* Copy the allocated blocks to the host, sorted ascending by (x, y, z).
  *   coords  HOST int32[capacity * 3] or NULL to only count

@@ -49,7 +49,7 @@ EXPORTED = ("itm_scene_create", "itm_scene_create_ex", "itm_scene_destroy", "itm
             "itm_refiner_create", "itm_refiner_destroy", "itm_refiner_set_stream",
             "itm_refiner_get_params", "itm_refiner_forward", "itm_refiner_gradient",
             "itm_refiner_train_step", "itm_gather_blocks", "itm_scene_set_refiner",
-            "itm_export_blocks_refined")
+            "itm_export_blocks_refined", "itm_scene_set_search_range", "itm_expected_depths")
 ITM_REFINE_PARAMS = 27712
 
 
@@ -84,6 +84,8 @@ def lib():
             "itm_gather_blocks": (C.c_int, [_P, _P, C.c_int64, _P]),
             "itm_scene_set_refiner": (C.c_int, [_P, _P, C.c_float]),
             "itm_export_blocks_refined": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+            "itm_scene_set_search_range": (C.c_int, [_P, C.c_int32, C.c_int32]),
+            "itm_expected_depths": (C.c_int, [_P, C.POINTER(itm_intrinsics), _P, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -167,6 +169,17 @@ def itm_raycast(h, K, T_wc, out_pts, out_normals):
     q = _dev(out_normals, "torch.float32", n)
     T, Tp = _pose(T_wc)
     _check(lib().itm_raycast(h, C.byref(Ki), Tp, p, q))
+
+
+def itm_scene_set_search_range(h, enable, tile_capacity=0):
+    _check(lib().itm_scene_set_search_range(h, 1 if enable else 0, int(tile_capacity)))
+
+
+def itm_expected_depths(h, K, T_wc, out):
+    Ki = _intr(K)
+    z = _dev(out, "torch.float32", Ki.width * Ki.height * 2)
+    T, Tp = _pose(T_wc)
+    _check(lib().itm_expected_depths(h, C.byref(Ki), Tp, z))
 
 
 def itm_export_blocks(h, values=True):
@@ -356,6 +369,23 @@ class Scene:
         self._sync_stream()
         itm_raycast(self.h, Ki, T_wc, out_pts, out_normals)
         return out_pts, out_normals
+
+    def set_search_range(self, enable=True, tile_capacity=0):
+        """Raycast inside each pixel's expected depth range (on) or over
+        [z_near, z_far] (off, the default)."""
+        self._sync_stream()
+        itm_scene_set_search_range(self.h, enable, tile_capacity)
+
+    def expected_depths(self, K, T_wc, out=None):
+        """[H, W, 2] float32 (z_min, z_max) per pixel from the last frame's visible
+        blocks at pose T_wc; (+inf, 0) where none projects."""
+        import torch
+        Ki = _intr(K)
+        if out is None:
+            out = torch.empty((Ki.height, Ki.width, 2), dtype=torch.float32, device="cuda")
+        self._sync_stream()
+        itm_expected_depths(self.h, Ki, T_wc, out)
+        return out
 
     def export(self, values=True):
         self._sync_stream()

@@ -102,7 +102,6 @@ __global__ __launch_bounds__(256) void k_alloc(AllocArgs a)
     const FrameGeom &g = a.fg;
     if (blockIdx.x == 0) {
         // per-frame counters, filled by k_integrate
-        if (threadIdx.x == 0) a.cnt->n_vis = 0;
         if (threadIdx.x < kStripes) {
             a.cnt->upd[0][threadIdx.x][0] = 0;
             a.cnt->vis[0][threadIdx.x][0] = 0;

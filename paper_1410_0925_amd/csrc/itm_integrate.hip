@@ -5,9 +5,9 @@
 // visibility flags, so no count is read back).  Lane l owns voxels 4l..4l+3 and
 // 256+4l..256+4l+3 of the block,
 // so every voxel load or store instruction of a wave covers one contiguous range
-// (16 B per lane in the float form).  A lane first decides, for its 8 voxels,
-// whether each is updated -- that needs only the voxel's position and the depth
-// image -- and reads and writes a group of 4 voxels only when one of them is.
+// (16 B per lane in the float form).  A lane reads its 8 voxels, decides for
+// each whether it is updated -- that needs only the voxel's position and the
+// depth image -- and writes back a group of 4 voxels only when one of them is.
 //
 // Decisions follow a fixed binary32 evaluation order (so that they can be
 // reproduced exactly): the block origin's camera coordinates are formed in binary64
@@ -103,18 +103,13 @@ struct Group4<ITM_VOX_S16U8> {
 
 // one visible block (entry e) by one wave; returns the lane's updated voxels
 template <int FMT>
-__device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane)
+__device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane, unsigned long long &key_out)
 {
     const FrameGeom &g = a.fg;
     unsigned long long key;
     int32_t ptr;
-    if (e < 2 * a.h.n_buckets) {
-        key = a.h.buckets[e >> 1].key[e & 1];
-        ptr = a.h.buckets[e >> 1].ptr[e & 1];
-    } else {
-        key = a.h.excess[e - 2 * a.h.n_buckets].key;
-        ptr = a.h.excess[e - 2 * a.h.n_buckets].ptr;
-    }
+    entry_at(a.h, e, key, ptr);
+    key_out = key;
     if (ptr < 0) return 0;  // cannot happen: every flagged entry owns a block
     int kx, ky, kz;
     unpack_key(key, kx, ky, kz);
@@ -132,6 +127,13 @@ __device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane)
     }
     const float mu = g.mu_f, inv_mu = 1.0f / mu;
     const int64_t vbase = (int64_t)ptr * kBlockVox;
+    // The voxels are loaded together with the depth reads instead of after
+    // them (the update decision needs only the depth image): one dependent
+    // memory round less, for about 6% more voxel bytes read (whole 128-byte
+    // lines are touched anyway).
+    Group4<FMT> vg[2];
+    vg[0].load(a.sdf, a.w, vbase + 4 * lane);
+    vg[1].load(a.sdf, a.w, vbase + 4 * lane + 256);
     uint32_t n_upd = 0;
 #pragma unroll
     for (int grp = 0; grp < 2; grp++) {
@@ -164,8 +166,7 @@ __device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane)
             upd |= 1u << j;
         }
         if (upd) {
-            Group4<FMT> v;
-            v.load(a.sdf, a.w, vbase + li0);
+            Group4<FMT> &v = vg[grp];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 if (!(upd & (1u << j))) continue;
@@ -183,35 +184,88 @@ __device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane)
     return n_upd;
 }
 
-__device__ __forceinline__ int bytes_set(uint32_t x) { return (int)((x * 0x01010101u) >> 24); }
-
 constexpr int kScanThreads = 256;
 constexpr int kScanEntries = kScanThreads * 8;   // flag bytes per workgroup
+static_assert(kScanEntries == kSegEntries, "one visible-list segment per workgroup");
+
+// Expected-depth rectangles of the workgroup's n visible blocks at the frame's
+// pose, appended to the bins of the tiles they overlap.  8 lanes per block take
+// its 8 box corners and merge them with a butterfly; 32 blocks per pass.  A
+// phase of its own after the integration, so that its binary64 temporaries do
+// not add to the integration's registers.
+__device__ void bin_blocks(const IntegrateArgs &a, const unsigned long long *keys, int n)
+{
+    const FrameGeom &g = a.fg;
+    const int grp = threadIdx.x >> 3, corner = threadIdx.x & 7;
+    for (int base = 0; base < n; base += kScanThreads / 8) {   // uniform
+        const int j = base + grp;
+        BoxAcc b;
+        if (j < n) {
+            int kx, ky, kz;
+            unpack_key(keys[j], kx, ky, kz);
+            box_corner(g, kx, ky, kz, corner, b);
+        } else {
+            b.zlo = b.xlo = b.ylo = INFINITY;
+            b.zhi = b.xhi = b.yhi = -INFINITY;
+            b.behind = false;
+        }
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) {
+            BoxAcc c;
+            c.zlo = __shfl_xor(b.zlo, o, kWave);
+            c.zhi = __shfl_xor(b.zhi, o, kWave);
+            c.xlo = __shfl_xor(b.xlo, o, kWave);
+            c.xhi = __shfl_xor(b.xhi, o, kWave);
+            c.ylo = __shfl_xor(b.ylo, o, kWave);
+            c.yhi = __shfl_xor(b.yhi, o, kWave);
+            c.behind = __shfl_xor((int)b.behind, o, kWave) != 0;
+            box_merge(b, c);
+        }
+        RangeRect r;
+        if (j < n && box_rect(g, b, r)) {
+            int tx0, ty0, ntx, n_tiles;
+            rect_tiles(r, tx0, ty0, ntx, n_tiles);
+            for (int t = corner; t < n_tiles; t += 8) {
+                const int tile = (ty0 + t / ntx) * a.rb.tw + tx0 + t % ntx;
+                const int slot = atomicAdd(&a.rb.cnt[tile], 1);
+                if (slot < a.rb.cap) a.rb.rect[(int64_t)tile * a.rb.cap + slot] = r;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ int bytes_set(uint32_t x) { return (int)((x * 0x01010101u) >> 24); }
+
 
 // Stage three of the allocation (the visible list) fused with the integration:
 // workgroup b scans flag bytes [2048 b, 2048 b + 2048), clears them, compacts
-// the set ones into an LDS list (wave prefix sums), and its 4 waves integrate
-// those blocks.  The hash spreads blocks uniformly over the entries, so every
+// the set ones into an LDS list (wave prefix sums) -- also written out as
+// segment b of the visible list -- and its 4 waves integrate those blocks.  The hash spreads blocks uniformly over the entries, so every
 // workgroup gets about the same share (about 4 blocks at VGA).  The same pass
 // clears the allocation's claim-set slots.
 template <int FMT>
 __global__ __launch_bounds__(kScanThreads) void k_integrate(IntegrateArgs a)
 {
     __shared__ int32_t s_list[kScanEntries];
+    __shared__ unsigned long long s_key[kScanEntries];   // block keys, for the range bins
     __shared__ int s_wave[kScanThreads / kWave];
-    __shared__ int s_n, s_base;
+    __shared__ int s_n;
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int nwaves = kScanThreads / kWave;
+    // scan and clear 8 flags per thread
+    const int64_t w8 = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
+    uint2 f = make_uint2(0u, 0u);
+    if (w8 < a.n_words8) f = a.vis8[w8];
     if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt->set_used[a.parity ^ 1] = 0;  // next frame's counter
     {
         const int su = a.cnt->set_used[a.parity];
         for (int i = blockIdx.x * kScanThreads + threadIdx.x; i < su; i += gridDim.x * kScanThreads)
             a.set[a.set_list[i]] = 0ull;
     }
-    // scan and clear 8 flags per thread
-    const int64_t w8 = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
-    uint2 f = make_uint2(0u, 0u);
-    if (w8 < a.n_words8) f = a.vis8[w8];
+    if (a.rb.cnt) {   // the next frame's bins
+        for (int i = blockIdx.x * kScanThreads + threadIdx.x; i < a.n_clear; i += gridDim.x * kScanThreads)
+            a.rb_clear[i] = 0;
+    }
     const int c = bytes_set(f.x) + bytes_set(f.y);
     if (c) a.vis8[w8] = make_uint2(0u, 0u);
     int incl = c;
@@ -230,30 +284,39 @@ __global__ __launch_bounds__(kScanThreads) void k_integrate(IntegrateArgs a)
             t += x;
         }
         s_n = t;
+        a.seg.cnt[blockIdx.x] = t;
         if (t) {
             const int sI = blockIdx.x % kStripes;
             atomicAdd(&a.cnt->vis[0][sI][0], (unsigned long long)t);
             atomicAdd(&a.cnt->vis[1][sI][0], (unsigned long long)t);
-            s_base = a.vis_list ? atomicAdd(&a.cnt->n_vis, t) : 0;
         }
     }
     __syncthreads();
     if (c) {
         int k = s_wave[wave] + incl - c;
+        int32_t *seg = a.seg.list + (int64_t)blockIdx.x * kSegEntries;
         const uint32_t w2[2] = {f.x, f.y};
 #pragma unroll
         for (int q = 0; q < 8; q++)
             if ((w2[q >> 2] >> (8 * (q & 3))) & 0xffu) {
                 const int32_t e = (int32_t)(w8 * 8 + q);
                 s_list[k] = e;
-                if (a.vis_list) a.vis_list[s_base + k] = e;
+                seg[k] = e;
                 k++;
             }
     }
     __syncthreads();
     const int n = s_n;
     uint32_t n_upd = 0;
-    for (int j = wave; j < n; j += nwaves) n_upd += integrate_block<FMT>(a, s_list[j], lane);
+    for (int j = wave; j < n; j += nwaves) {
+        unsigned long long key;
+        n_upd += integrate_block<FMT>(a, s_list[j], lane, key);
+        if (a.rb.cnt && lane == 0) s_key[j] = key;
+    }
+    if (a.rb.cnt) {
+        __syncthreads();
+        bin_blocks(a, s_key, n);
+    }
     // one counter update per workgroup, on one of kStripes separate lines
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) n_upd += __shfl_xor(n_upd, o, kWave);

@@ -7,7 +7,13 @@
 //            the paper keeps in the bucket's last entry
 //   excess   n_excess x 16 B    {key (u64), ptr (i32), next (i32)}  unordered part
 //   vis      n_entries bytes    per-entry visibility flag of the current frame
-//   vis_list n_entries x i32    compacted visible entry ids (for the refiner gate)
+//   vis_list n_entries x i32    the frame's visible entry ids, one segment per
+//                               2048 entries: segment b holds the ids flagged in
+//                               entries [2048 b, 2048 b + 2048), compacted to its
+//                               front; seg_cnt[b] says how many
+//   bins     3 x n_tiles x (4 B + cap x 16 B)   expected-depth rectangles binned
+//                               by 16 x 16 pixel tile (two frame parities + one
+//                               for raycasts at another pose)
 //   sdf, w   capacity x 512     voxel block array, structure of arrays, one
 //                               element type per storage form
 //   set      R x u64            per-frame set of blocks claimed for the excess list
@@ -48,7 +54,7 @@ static_assert(sizeof(Excess) == 16, "excess record is 16 bytes");
 struct Counters {
     int32_t vba_next;       // voxel blocks handed out (bump allocator = free stack pop)
     int32_t excess_next;    // excess entries handed out (may run past n_excess)
-    int32_t n_vis;          // entries in the visible list (written only when a consumer needs it)
+    int32_t pad0;
     int32_t set_used[2];    // claim-set slots used, by frame parity
     int32_t pad;
     unsigned long long dropped_total;
@@ -196,6 +202,34 @@ struct AllocArgs {
     Counters *cnt;
 };
 
+// The visible list in segments (see the layout above); written by the
+// integration kernel, read by the refiner gate and the expected-depth binning.
+constexpr int kSegEntries = 2048;
+struct VisSegments {
+    int32_t *list;        // [n_seg][kSegEntries]
+    int32_t *cnt;         // [n_seg]
+    int32_t n_seg;
+};
+
+// Expected depth ranges (section "Raycast", search range).  Each visible block's
+// box -- the region [8k - 1/2, 8k + 7 1/2] s whose samples read the block -- is
+// projected; its 2D bounding box gets the box's camera depth range.  The
+// rectangles are binned by 16 x 16 pixel tile; a tile's pixels take the min and
+// max over the rectangles covering them.
+struct alignas(16) RangeRect {
+    int16_t u0, u1, v0, v1;   // inclusive pixel rectangle, clipped to the image
+    float z0, z1;             // camera depth range, rounded outwards to binary32
+};
+static_assert(sizeof(RangeRect) == 16, "range rectangle is 16 bytes");
+constexpr int kTile = 16;
+
+struct RangeBins {
+    int32_t *cnt;         // [n_tiles] rectangles appended (may exceed cap)
+    RangeRect *rect;      // [n_tiles][cap]
+    int32_t cap;
+    int32_t tw, th;       // tiles per row, per column
+};
+
 struct IntegrateArgs {
     FrameGeom fg;
     const float *depth;
@@ -205,7 +239,10 @@ struct IntegrateArgs {
     unsigned long long *set;  // claim set of the allocation (cleared here)
     const int32_t *set_list;
     int32_t parity;           // frame parity: which claim counter this frame used
-    int32_t *vis_list;        // written when non-null (a later kernel consumes it)
+    VisSegments seg;          // the visible list, written here
+    RangeBins rb;             // rb.cnt non-null: bin this frame's rectangles (pose of the frame)
+    int32_t *rb_clear;        // counts of the other parity, cleared here (with rb)
+    int32_t n_clear;
     void *sdf;
     void *w;
     Counters *cnt;
@@ -217,6 +254,8 @@ struct RaycastArgs {
     const void *sdf;
     float4 *pts;
     float4 *nrm;
+    RangeBins rb;             // rb.cnt non-null: search each ray inside its expected range
+    VisSegments seg;          // for tiles whose bin overflowed
 };
 
 // learned refiner (itm_refine.hip)
@@ -243,8 +282,7 @@ struct RefineArgs {
 struct RefineGateArgs {
     RefineParams P;
     HashView h;
-    const int32_t *vis_list;
-    const Counters *cnt;
+    VisSegments seg;
     const void *sdf;
     const void *w;
     float inv_max_w;
@@ -263,6 +301,12 @@ hipError_t launch_refine_adam(float *master, float *m, float *v, const float *gr
 hipError_t launch_refine_cast(const float *master, uint16_t *Wf, uint16_t *Wt, float *bias, hipStream_t st);
 hipError_t launch_refine_gather(int fmt, const HashView &h, const void *sdf, const void *w, const int32_t *coords,
                                 int64_t n, float inv_max_w, float *out, hipStream_t st);
+
+hipError_t launch_range_clear(int32_t *cnt, int n, hipStream_t st);
+hipError_t launch_range_bin(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
+                            hipStream_t st);
+hipError_t launch_range_image(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
+                              float2 *zr, hipStream_t st);
 
 // launchers (one translation unit each)
 hipError_t launch_alloc(const AllocArgs &a, hipStream_t st);
@@ -325,6 +369,178 @@ __device__ __forceinline__ int32_t find_block_direct(const HashView &h, int x, i
         x_i = E.next;
     }
     return -1;
+}
+
+// key and block pointer of hash entry e (entry ids as in the layout above)
+__device__ __forceinline__ void entry_at(const HashView &h, int32_t e, unsigned long long &key, int32_t &ptr)
+{
+    if (e < 2 * h.n_buckets) {
+        key = h.buckets[e >> 1].key[e & 1];
+        ptr = h.buckets[e >> 1].ptr[e & 1];
+    } else {
+        key = h.excess[e - 2 * h.n_buckets].key;
+        ptr = h.excess[e - 2 * h.n_buckets].ptr;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// expected depth ranges: per-block rectangle (binary64, fixed order: corner
+// ((8 k - 1/2) + 8 c) s, camera ((R0 X0 + R1 X1) + R2 X2) + t, pixel
+// fx X / Z + cx) and per-pixel min / max over a tile's rectangles
+// ---------------------------------------------------------------------------
+struct BoxAcc {
+    double zlo, zhi, xlo, xhi, ylo, yhi;
+    bool behind;
+};
+
+__device__ __forceinline__ void box_corner(const FrameGeom &g, int kx, int ky, int kz, int c, BoxAcc &b)
+{
+    const double X0 = ((double)(8 * kx) - 0.5 + ((c & 1) ? 8.0 : 0.0)) * g.s;
+    const double X1 = ((double)(8 * ky) - 0.5 + ((c & 2) ? 8.0 : 0.0)) * g.s;
+    const double X2 = ((double)(8 * kz) - 0.5 + ((c & 4) ? 8.0 : 0.0)) * g.s;
+    double P[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        double w = g.Rcw[3 * a + 0] * X0;
+        w = w + g.Rcw[3 * a + 1] * X1;
+        w = w + g.Rcw[3 * a + 2] * X2;
+        P[a] = w + g.tcw[a];
+    }
+    b.zlo = P[2];
+    b.zhi = P[2];
+    b.behind = !(P[2] > 0.0);
+    if (b.behind) {
+        b.xlo = b.ylo = INFINITY;
+        b.xhi = b.yhi = -INFINITY;
+    } else {
+        b.xlo = b.xhi = g.fxd * P[0] / P[2] + g.cxd;
+        b.ylo = b.yhi = g.fyd * P[1] / P[2] + g.cyd;
+    }
+}
+
+__device__ __forceinline__ void box_merge(BoxAcc &a, const BoxAcc &b)
+{
+    a.zlo = fmin(a.zlo, b.zlo); a.zhi = fmax(a.zhi, b.zhi);
+    a.xlo = fmin(a.xlo, b.xlo); a.xhi = fmax(a.xhi, b.xhi);
+    a.ylo = fmin(a.ylo, b.ylo); a.yhi = fmax(a.yhi, b.yhi);
+    a.behind = a.behind || b.behind;
+}
+
+// false when the rectangle misses the image
+__device__ __forceinline__ bool box_rect(const FrameGeom &g, const BoxAcc &b, RangeRect &r)
+{
+    double zlo = b.zlo;
+    if (b.behind) {
+        // a corner at or behind the camera plane: the whole image, from depth 0
+        r.u0 = 0; r.u1 = (int16_t)(g.W - 1); r.v0 = 0; r.v1 = (int16_t)(g.H - 1);
+        zlo = 0.0;
+    } else {
+        const double a0 = ceil(b.xlo), a1 = floor(b.xhi), b0 = ceil(b.ylo), b1 = floor(b.yhi);
+        if (a1 < 0.0 || b1 < 0.0 || a0 > (double)(g.W - 1) || b0 > (double)(g.H - 1) || a0 > a1 || b0 > b1)
+            return false;
+        r.u0 = (int16_t)(a0 < 0.0 ? 0 : (int)a0);
+        r.v0 = (int16_t)(b0 < 0.0 ? 0 : (int)b0);
+        r.u1 = (int16_t)(a1 > (double)(g.W - 1) ? g.W - 1 : (int)a1);
+        r.v1 = (int16_t)(b1 > (double)(g.H - 1) ? g.H - 1 : (int)b1);
+    }
+    r.z0 = __double2float_rd(zlo);
+    r.z1 = __double2float_ru(b.zhi);
+    return true;
+}
+
+// one thread, all 8 corners
+__device__ __forceinline__ bool block_rect(const FrameGeom &g, int kx, int ky, int kz, RangeRect &r)
+{
+    BoxAcc acc;
+    box_corner(g, kx, ky, kz, 0, acc);
+#pragma unroll 1
+    for (int c = 1; c < 8; c++) {
+        BoxAcc b;
+        box_corner(g, kx, ky, kz, c, b);
+        box_merge(acc, b);
+    }
+    return box_rect(g, acc, r);
+}
+
+__device__ __forceinline__ void rect_tiles(const RangeRect &r, int &tx0, int &ty0, int &ntx, int &n)
+{
+    tx0 = r.u0 / kTile;
+    ty0 = r.v0 / kTile;
+    ntx = r.u1 / kTile - tx0 + 1;
+    n = ntx * (r.v1 / kTile - ty0 + 1);
+}
+
+// LDS of the per-tile range computation
+struct RangeLds {
+    union {
+        RangeRect rect[256];
+        struct {
+            uint32_t zlo[256], zhi[256];   // binary32 bits (all values >= 0: integer order = float order)
+        } px;
+    };
+};
+
+// Range of pixel (u, v) of tile (tx, ty) -- whole workgroup of 256 threads, one
+// pixel each (any mapping; (u, v) may lie outside the image).  Returns the empty
+// range (+inf, 0) where no rectangle covers the pixel.  A tile whose bin
+// overflowed recomputes every visible block's rectangle from the visible list.
+__device__ inline void tile_range(const FrameGeom &g, const HashView &h, const VisSegments &seg,
+                                  const RangeBins &rb, int tx, int ty, int u, int v, RangeLds &L, float &zlo,
+                                  float &zhi)
+{
+    const int tile = ty * rb.tw + tx;
+    const int n = rb.cnt[tile];
+    zlo = INFINITY;
+    zhi = 0.0f;
+    if (n <= rb.cap) {
+        for (int base = 0; base < n; base += 256) {
+            __syncthreads();
+            if (base + (int)threadIdx.x < n) L.rect[threadIdx.x] = rb.rect[(int64_t)tile * rb.cap + base + threadIdx.x];
+            __syncthreads();
+            const int m = min(256, n - base);
+            for (int j = 0; j < m; j++) {
+                const RangeRect r = L.rect[j];
+                if (u >= r.u0 && u <= r.u1 && v >= r.v0 && v <= r.v1) {
+                    zlo = fminf(zlo, r.z0);
+                    zhi = fmaxf(zhi, r.z1);
+                }
+            }
+        }
+        return;
+    }
+    // overflow: every visible block, rectangles clipped to the tile, min / max
+    // by LDS atomics (threads stride over the list's segments)
+    __syncthreads();
+    L.px.zlo[threadIdx.x] = __float_as_uint(INFINITY);
+    L.px.zhi[threadIdx.x] = 0u;
+    __syncthreads();
+    const int ux0 = tx * kTile, vy0 = ty * kTile;
+    for (int sg = threadIdx.x; sg < seg.n_seg; sg += blockDim.x) {
+        const int c = seg.cnt[sg];
+        for (int i = 0; i < c; i++) {
+            unsigned long long key;
+            int32_t ptr;
+            entry_at(h, seg.list[(int64_t)sg * kSegEntries + i], key, ptr);
+            int kx, ky, kz;
+            unpack_key(key, kx, ky, kz);
+            RangeRect r;
+            if (!block_rect(g, kx, ky, kz, r)) continue;
+            const int a0 = max((int)r.u0, ux0), a1 = min((int)r.u1, ux0 + kTile - 1);
+            const int b0 = max((int)r.v0, vy0), b1 = min((int)r.v1, vy0 + kTile - 1);
+            for (int y = b0; y <= b1; y++)
+                for (int x = a0; x <= a1; x++) {
+                    const int p = (y - vy0) * kTile + (x - ux0);
+                    atomicMin(&L.px.zlo[p], __float_as_uint(r.z0));
+                    atomicMax(&L.px.zhi[p], __float_as_uint(r.z1));
+                }
+        }
+    }
+    __syncthreads();
+    if (u >= ux0 && u < ux0 + kTile && v >= vy0 && v < vy0 + kTile) {
+        zlo = __uint_as_float(L.px.zlo[(v - vy0) * kTile + (u - ux0)]);
+        zhi = __uint_as_float(L.px.zhi[(v - vy0) * kTile + (u - ux0)]);
+    }
+    __syncthreads();
 }
 
 }  // namespace itm

@@ -1,0 +1,80 @@
+// Expected depth ranges (section "Raycast", the search range; the paper's
+// CreateExpectedDepths): the visible blocks are forward-projected and each
+// pixel gets the min and max camera depth of the block boxes covering it.
+//
+// The paper splits this into a fragment list (16 x 16 pixel pieces of every
+// block's bounding box, counted with a prefix sum) and a render pass that
+// updates per-pixel min / max with atomics.  Here every block's rectangle is
+// appended to the bin of each 16 x 16 tile it overlaps (one atomic per block
+// and tile, no per-pixel atomics), and the raycast's workgroup for a tile --
+// which covers exactly those 16 x 16 pixels -- takes the min / max over its bin
+// in registers, so the range image itself never goes through memory.  The
+// integration kernel bins at the frame's own pose as it integrates each block;
+// k_range_bin does it for a raycast at any other pose, from the visible list.
+#include <algorithm>
+
+#include "itm_internal.hpp"
+
+namespace itm {
+
+__global__ __launch_bounds__(256) void k_range_clear(int32_t *cnt, int n)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cnt[i] = 0;
+}
+
+// workgroup b bins the blocks of visible-list segment b, one thread per block
+__global__ __launch_bounds__(256) void k_range_bin(FrameGeom g, HashView h, VisSegments seg, RangeBins rb)
+{
+    const int sg = blockIdx.x;
+    const int c = seg.cnt[sg];
+    for (int i = threadIdx.x; i < c; i += blockDim.x) {
+        unsigned long long key;
+        int32_t ptr;
+        entry_at(h, seg.list[(int64_t)sg * kSegEntries + i], key, ptr);
+        int kx, ky, kz;
+        unpack_key(key, kx, ky, kz);
+        RangeRect r;
+        if (!block_rect(g, kx, ky, kz, r)) continue;
+        int tx0, ty0, ntx, n;
+        rect_tiles(r, tx0, ty0, ntx, n);
+        for (int t = 0; t < n; t++) {
+            const int tile = (ty0 + t / ntx) * rb.tw + tx0 + t % ntx;
+            const int slot = atomicAdd(&rb.cnt[tile], 1);
+            if (slot < rb.cap) rb.rect[(int64_t)tile * rb.cap + slot] = r;
+        }
+    }
+}
+
+// the range image: one workgroup per tile, row-major pixels within it
+__global__ __launch_bounds__(256) void k_range_image(FrameGeom g, HashView h, VisSegments seg, RangeBins rb,
+                                                      float2 *zr)
+{
+    __shared__ RangeLds L;
+    const int tx = blockIdx.x % rb.tw, ty = blockIdx.x / rb.tw;
+    const int u = tx * kTile + (threadIdx.x & (kTile - 1)), v = ty * kTile + threadIdx.x / kTile;
+    float zlo, zhi;
+    tile_range(g, h, seg, rb, tx, ty, u, v, L, zlo, zhi);
+    if (u < g.W && v < g.H) zr[(int64_t)v * g.W + u] = make_float2(zlo, zhi);
+}
+
+hipError_t launch_range_clear(int32_t *cnt, int n, hipStream_t st)
+{
+    k_range_clear<<<std::max(1, std::min((n + 255) / 256, 1024)), 256, 0, st>>>(cnt, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_range_bin(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
+                            hipStream_t st)
+{
+    k_range_bin<<<seg.n_seg, 256, 0, st>>>(g, h, seg, rb);
+    return hipGetLastError();
+}
+
+hipError_t launch_range_image(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
+                              float2 *zr, hipStream_t st)
+{
+    k_range_image<<<rb.tw * rb.th, 256, 0, st>>>(g, h, seg, rb, zr);
+    return hipGetLastError();
+}
+
+}  // namespace itm

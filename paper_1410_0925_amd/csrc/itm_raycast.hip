@@ -2,6 +2,9 @@
 //
 // Ray set-up (origin, unit direction, search range) is binary64 and rounded once;
 // the march is binary32 in voxel units, q(t) = o/s + t d/s with t in metres.
+// The search range is [z_near, z_far] along the camera axis or, with expected
+// depths on, that range narrowed to the pixel's expected range (section
+// "Raycast": visible blocks projected into the image).
 // Reads:
 //   nearest  n(q) = floor(q + 1/2); found when the block of n is allocated;
 //            F_n = F at n
@@ -143,6 +146,12 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int u = tx * 16 + (wave & 1) * 8 + (lane & 7);
     const int v = ty * 16 + (wave >> 1) * 8 + (lane >> 3);
+    // expected depth range of the pixel (whole workgroup)
+    float zlo = 0.0f, zhi = 0.0f;
+    if (a.rb.cnt) {
+        __shared__ RangeLds s_range;
+        tile_range(g, a.h, a.seg, a.rb, tx, ty, u, v, s_range, zlo, zhi);
+    }
     if (u >= g.W || v >= g.H) return;
     const int64_t pix = (int64_t)v * g.W + u;
 
@@ -154,7 +163,17 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     for (int c = 0; c < 3; c++) dir[c] = (g.Rwc[3 * c] * cdx + g.Rwc[3 * c + 1] * cdy + g.Rwc[3 * c + 2]) / len;
     const float ox = (float)(g.twc[0] / g.s), oy = (float)(g.twc[1] / g.s), oz = (float)(g.twc[2] / g.s);
     const float dx = (float)(dir[0] / g.s), dy = (float)(dir[1] / g.s), dz = (float)(dir[2] / g.s);
-    const float t_near = (float)((double)g.z_near * len), t_far = (float)((double)g.z_far * len);
+    // search range: [z_near, z_far], narrowed to the expected range when there is one
+    double t0 = (double)g.z_near * len, t1 = (double)g.z_far * len;
+    if (a.rb.cnt) {
+        if (zlo <= zhi) {
+            t0 = fmax(t0, (double)zlo * len);
+            t1 = fmin(t1, (double)zhi * len);
+        } else {
+            t1 = t0;   // no visible block projects here: nothing to search
+        }
+    }
+    const float t_near = (float)t0, t_far = (float)t1;
     const float s = g.s_f, mu = g.mu_f, bs = 8.0f * g.s_f;
     const int fine_budget = (int)ceilf(bs / mu) + 1;
     const int cap = (int)((t_far - t_near) / s) * 4 + 1000;

@@ -350,18 +350,13 @@ __global__ __launch_bounds__(256) void k_refine_gated(RefineGateArgs a)
     const auto *Wv = (const typename V::Wt *)a.w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, n = lane & 15;
-    const int n_vis = a.cnt->n_vis;
-    for (int bi = blockIdx.x; bi < n_vis; bi += gridDim.x) {
-        const int32_t e = a.vis_list[bi];
+    // the visible list, segment by segment (workgroup-uniform loops)
+    for (int sg = blockIdx.x; sg < a.seg.n_seg; sg += gridDim.x)
+    for (int si = 0, sn = a.seg.cnt[sg]; si < sn; si++) {
+        const int32_t e = a.seg.list[(int64_t)sg * kSegEntries + si];
         unsigned long long key;
         int32_t ptr;
-        if (e < 2 * a.h.n_buckets) {
-            key = a.h.buckets[e >> 1].key[e & 1];
-            ptr = a.h.buckets[e >> 1].ptr[e & 1];
-        } else {
-            key = a.h.excess[e - 2 * a.h.n_buckets].key;
-            ptr = a.h.excess[e - 2 * a.h.n_buckets].ptr;
-        }
+        entry_at(a.h, e, key, ptr);
         int kx, ky, kz;
         unpack_key(key, kx, ky, kz);
         // gate on the block's largest weight

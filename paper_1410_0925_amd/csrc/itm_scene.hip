@@ -72,7 +72,9 @@ struct itm_scene {
     Excess *excess = nullptr;
     uint8_t *vis = nullptr;
     int64_t vis_bytes = 0;
-    int32_t *vis_list = nullptr;
+    int32_t *vis_list = nullptr;      // [n_seg][kSegEntries]
+    int32_t *seg_cnt = nullptr;       // [n_seg]
+    int32_t n_seg = 0;
     void *sdf = nullptr;
     void *w = nullptr;
     unsigned long long *set = nullptr;
@@ -86,6 +88,17 @@ struct itm_scene {
     __half *refined = nullptr;        // [vba_cap][512], allocated on attach
     int32_t *stamp = nullptr;         // [vba_cap]
     int32_t frame = 0;
+
+    // expected depth ranges: bins for parity 0, parity 1 (filled by the
+    // integration at its pose) and 2 (filled for a raycast at another pose)
+    bool range_on = false;
+    int32_t range_cap = 512;
+    int32_t *bin_cnt = nullptr;       // [3][bin_tiles]
+    RangeRect *bin_rect = nullptr;    // [3][bin_tiles][range_cap]
+    int64_t bin_tiles = 0;
+    int32_t fused_frame = -1;         // frame whose own-pose bins are valid, -1 none
+    itm_intrinsics fused_K = {};
+    double fused_T[16] = {};
 
     bool prof = false;
     std::vector<hipEvent_t> ev;     // 2 per slot
@@ -109,6 +122,9 @@ void release(itm_scene *sc)
     (void)hipFree(sc->excess);
     (void)hipFree(sc->vis);
     (void)hipFree(sc->vis_list);
+    (void)hipFree(sc->seg_cnt);
+    (void)hipFree(sc->bin_cnt);
+    (void)hipFree(sc->bin_rect);
     (void)hipFree(sc->sdf);
     (void)hipFree(sc->w);
     (void)hipFree(sc->set);
@@ -172,6 +188,69 @@ itm_status make_geom(const itm_scene *sc, const itm_intrinsics *K, const double 
     g->max_w_f = (float)sc->max_w;
     g->z_near = sc->z_near;
     g->z_far = sc->z_far;
+    return ITM_OK;
+}
+
+VisSegments segments(const itm_scene *sc)
+{
+    VisSegments v;
+    v.list = sc->vis_list;
+    v.cnt = sc->seg_cnt;
+    v.n_seg = sc->n_seg;
+    return v;
+}
+
+// bins for images of W x H pixels (grown on demand; growing clears them)
+itm_status ensure_bins(itm_scene *sc, int W, int H)
+{
+    const int64_t tiles = (int64_t)((W + kTile - 1) / kTile) * ((H + kTile - 1) / kTile);
+    if (sc->bin_cnt && tiles <= sc->bin_tiles) return ITM_OK;
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    (void)hipFree(sc->bin_cnt);
+    (void)hipFree(sc->bin_rect);
+    sc->bin_cnt = nullptr;
+    sc->bin_rect = nullptr;
+    sc->bin_tiles = 0;
+    sc->fused_frame = -1;
+    if (itm_status st = dev_alloc((void **)&sc->bin_cnt, sizeof(int32_t) * 3 * tiles, "range bin counts")) return st;
+    if (itm_status st = dev_alloc((void **)&sc->bin_rect, sizeof(RangeRect) * 3 * tiles * sc->range_cap,
+                                  "range bins"))
+        return st;
+    sc->bin_tiles = tiles;
+    HIP_TRY(launch_range_clear(sc->bin_cnt, (int)(3 * tiles), sc->stream));
+    return ITM_OK;
+}
+
+RangeBins bin_set(const itm_scene *sc, int set, int W, int H)
+{
+    RangeBins rb;
+    rb.cnt = sc->bin_cnt + (int64_t)set * sc->bin_tiles;
+    rb.rect = sc->bin_rect + (int64_t)set * sc->bin_tiles * sc->range_cap;
+    rb.cap = sc->range_cap;
+    rb.tw = (W + kTile - 1) / kTile;
+    rb.th = (H + kTile - 1) / kTile;
+    return rb;
+}
+
+HashView hash_view(const itm_scene *sc);
+
+// the bins holding the last frame's visible blocks at pose (K, T): the frame's
+// own bins when it was integrated at exactly this pose and image size, else
+// set 2, filled now
+itm_status bins_for_pose(itm_scene *sc, const itm_intrinsics *K, const double *T, const FrameGeom &g,
+                         RangeBins *rb)
+{
+    if (itm_status st = ensure_bins(sc, g.W, g.H)) return st;
+    const bool same = sc->fused_frame >= 0 && sc->fused_frame == sc->frame - 1 &&
+                      std::memcmp(&sc->fused_K, K, sizeof *K) == 0 &&
+                      std::memcmp(sc->fused_T, T, sizeof sc->fused_T) == 0;
+    if (same) {
+        *rb = bin_set(sc, sc->fused_frame & 1, g.W, g.H);
+        return ITM_OK;
+    }
+    *rb = bin_set(sc, 2, g.W, g.H);
+    HIP_TRY(launch_range_clear(rb->cnt, rb->tw * rb->th, sc->stream));
+    HIP_TRY(launch_range_bin(g, hash_view(sc), segments(sc), *rb, sc->stream));
     return ITM_OK;
 }
 
@@ -290,10 +369,13 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
     sc->num_cu = prop.multiProcessorCount;
     const int64_t n_vox = sc->vba_cap * kBlockVox;
     sc->vis_bytes = (sc->n_entries + 15) / 16 * 16;
+    // one visible-list segment per integration workgroup (2048 flag bytes)
+    sc->n_seg = (int32_t)((sc->vis_bytes + kSegEntries - 1) / kSegEntries);
     if (dev_alloc((void **)&sc->buckets, sizeof(Bucket) * n_buckets, "buckets") ||
         dev_alloc((void **)&sc->excess, sizeof(Excess) * std::max<int64_t>(n_excess, 1), "excess") ||
         dev_alloc((void **)&sc->vis, sc->vis_bytes, "vis") ||
-        dev_alloc((void **)&sc->vis_list, sizeof(int32_t) * sc->n_entries, "vis_list") ||
+        dev_alloc((void **)&sc->vis_list, sizeof(int32_t) * kSegEntries * sc->n_seg, "vis_list") ||
+        dev_alloc((void **)&sc->seg_cnt, sizeof(int32_t) * sc->n_seg, "visible segment counts") ||
         dev_alloc(&sc->sdf, sdf_elem(fmt) * n_vox, "sdf") ||
         dev_alloc(&sc->w, w_elem(fmt) * n_vox, "weights") ||
         dev_alloc((void **)&sc->set, sizeof(unsigned long long) * sc->set_size, "claim set") ||
@@ -309,6 +391,7 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
     hipError_t e = launch_init(sc->buckets, n_buckets, sc->excess, n_excess, sc->vis, sc->vis_bytes,
                                sc->set, sc->set_size, sc->occ, sc->occ_words + kMacroWords + kBlockFilterWords,
                                sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
+    if (e == hipSuccess) e = launch_range_clear(sc->seg_cnt, sc->n_seg, sc->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     if (e != hipSuccess) {
         fail(ITM_ERR_HIP, "scene initialisation failed: %s", hipGetErrorString(e));
@@ -341,6 +424,8 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
     if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
     const HashView h = hash_view(sc);
     const int32_t parity = sc->frame & 1;
+    if (sc->range_on)
+        if (itm_status st = ensure_bins(sc, g.W, g.H)) return st;
     {
         ProfScope ps(sc, 0);
         AllocArgs a;
@@ -366,11 +451,24 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
         ia.set = sc->set;
         ia.set_list = sc->set_list;
         ia.parity = parity;
-        ia.vis_list = sc->refiner ? sc->vis_list : nullptr;   // the refiner gate reads the list
+        ia.seg = segments(sc);
+        ia.rb = RangeBins{};
+        ia.rb_clear = nullptr;
+        ia.n_clear = 0;
+        if (sc->range_on) {   // bin the expected-depth rectangles at this pose
+            ia.rb = bin_set(sc, parity, g.W, g.H);
+            ia.rb_clear = bin_set(sc, parity ^ 1, g.W, g.H).cnt;
+            ia.n_clear = (int32_t)sc->bin_tiles;
+        }
         ia.sdf = sc->sdf;
         ia.w = sc->w;
         ia.cnt = sc->cnt;
         HIP_TRY(launch_integrate(sc->fmt, ia, sc->stream));
+    }
+    sc->fused_frame = sc->range_on ? sc->frame : -1;
+    if (sc->range_on) {
+        sc->fused_K = *K;
+        std::memcpy(sc->fused_T, T_wc, sizeof sc->fused_T);
     }
     sc->frame++;
     if (sc->refiner) {
@@ -379,8 +477,7 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
         ra.P.Wt = sc->refiner->Wt;
         ra.P.bias = sc->refiner->bias;
         ra.h = h;
-        ra.vis_list = sc->vis_list;
-        ra.cnt = sc->cnt;
+        ra.seg = segments(sc);
         ra.sdf = sc->sdf;
         ra.w = sc->w;
         ra.inv_max_w = 1.0f / (float)sc->max_w;
@@ -409,7 +506,45 @@ itm_status itm_raycast(itm_scene *sc, const itm_intrinsics *K, const double *T_w
     a.sdf = sc->sdf;
     a.pts = reinterpret_cast<float4 *>(out_pts);
     a.nrm = reinterpret_cast<float4 *>(out_normals);
+    a.rb = RangeBins{};
+    a.seg = segments(sc);
+    if (sc->range_on)
+        if (itm_status st = bins_for_pose(sc, K, T_wc, g, &a.rb)) return st;
     HIP_TRY(launch_raycast(sc->fmt, a, sc->stream));
+    return ITM_OK;
+}
+
+itm_status itm_scene_set_search_range(itm_scene *sc, int32_t enable, int32_t tile_capacity)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    const int32_t cap = tile_capacity <= 0 ? 512 : tile_capacity;
+    if (cap > (1 << 16)) return fail(ITM_ERR_ARG, "tile capacity %d > 65536", tile_capacity);
+    if (cap != sc->range_cap && sc->bin_cnt) {   // reallocated at the next use
+        HIP_TRY(hipStreamSynchronize(sc->stream));
+        (void)hipFree(sc->bin_cnt);
+        (void)hipFree(sc->bin_rect);
+        sc->bin_cnt = nullptr;
+        sc->bin_rect = nullptr;
+        sc->bin_tiles = 0;
+    }
+    sc->range_cap = cap;
+    if (enable && !sc->range_on && sc->bin_cnt)   // counts left from an earlier period
+        HIP_TRY(launch_range_clear(sc->bin_cnt, (int)(3 * sc->bin_tiles), sc->stream));
+    sc->range_on = enable != 0;
+    sc->fused_frame = -1;
+    return ITM_OK;
+}
+
+itm_status itm_expected_depths(itm_scene *sc, const itm_intrinsics *K, const double *T_wc, float *zrange)
+{
+    if (!sc || !zrange) return fail(ITM_ERR_ARG, "NULL scene or output");
+    if ((uintptr_t)zrange & 7u) return fail(ITM_ERR_ARG, "output must be 8-byte aligned");
+    FrameGeom g;
+    if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
+    RangeBins rb;
+    if (itm_status st = bins_for_pose(sc, K, T_wc, g, &rb)) return st;
+    HIP_TRY(launch_range_image(g, hash_view(sc), segments(sc), rb, reinterpret_cast<float2 *>(zrange),
+                               sc->stream));
     return ITM_OK;
 }
 

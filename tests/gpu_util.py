@@ -20,10 +20,13 @@ def K_of(stream):
     return tuple(stream.intrinsics) + (stream.width, stream.height)
 
 
-def fuse_gpu(stream, frames=None, fmt="f32", params=None, ray_frames=(), per_frame_stats=False):
+def fuse_gpu(stream, frames=None, fmt="f32", params=None, ray_frames=(), per_frame_stats=False,
+             search_range=False, tile_capacity=0):
     itm, torch = gpu()
     n = stream.n_frames if frames is None else frames
     sc = itm.Scene.from_params(params or stream.params, fmt=fmt)
+    if search_range:
+        sc.set_search_range(True, tile_capacity)
     depth = torch.from_numpy(np.ascontiguousarray(stream.depth[:n])).cuda()
     K = K_of(stream)
     rays, stats = {}, []
@@ -38,7 +41,7 @@ def fuse_gpu(stream, frames=None, fmt="f32", params=None, ray_frames=(), per_fra
     return sc, rays, stats
 
 
-def fuse_oracle(stream, frames=None, params=None, ray_frames=(), per_frame_stats=False):
+def fuse_oracle(stream, frames=None, params=None, ray_frames=(), per_frame_stats=False, search_range=False):
     import oracle
     n = stream.n_frames if frames is None else frames
     sc = oracle.Scene.from_params(params or stream.params)
@@ -48,7 +51,9 @@ def fuse_oracle(stream, frames=None, params=None, ray_frames=(), per_frame_stats
         if per_frame_stats:
             stats.append(sc.stats())
         if f in ray_frames:
-            rays[f] = sc.raycast(stream.width, stream.height, stream.intrinsics, stream.T_wc[f])
+            args = (stream.width, stream.height, stream.intrinsics, stream.T_wc[f])
+            zr = sc.expected_depths(*args) if search_range else None
+            rays[f] = sc.raycast(*args, zrange=zr)
     return sc, rays, stats
 
 
@@ -62,6 +67,37 @@ def compare_volumes(g_export, o_export, tol=SDF_TOL):
     err = np.abs(gF.astype(np.float64) - oF)
     assert err.max() <= tol, f"max |dF| {err.max():.3e} > {tol}"
     return float(err.max()), float(np.sqrt(np.mean(err[oW > 0] ** 2))) if (oW > 0).any() else 0.0
+
+
+def ragged_stream():
+    """4 frames of a 97 x 61 image (not a multiple of the 16 x 16 tile) of a
+    sphere before a plane, with NaN / inf / negative / zero pixels."""
+    from synth import Scene as SynthScene, pose_look_at, render_depth
+    rng = np.random.default_rng(3)
+    K = (80.0, 80.0, 48.3, 30.1)
+    scene = SynthScene(spheres=np.array([[0.1, -0.05, 1.0, 0.25]]),
+                       planes=np.array([[0.0, 0.0, -1.0, -1.6]]))
+    frames, poses = [], []
+    for a in np.linspace(-0.1, 0.1, 4):
+        T = pose_look_at((a, 0.02, 0.0), (0.1, -0.05, 1.0), (0, -1, 0))
+        d = render_depth(scene, K, 97, 61, T).astype(np.float32)
+        d += (rng.standard_normal(d.shape) * 0.001).astype(np.float32)
+        bad = rng.random(d.shape)
+        d[bad < 0.02] = np.nan
+        d[(bad >= 0.02) & (bad < 0.03)] = np.inf
+        d[(bad >= 0.03) & (bad < 0.04)] = -1.0
+        d[(bad >= 0.04) & (bad < 0.05)] = 0.0
+        frames.append(d)
+        poses.append(T)
+
+    class S:  # minimal stream object
+        pass
+    st = S()
+    st.depth, st.T_wc = np.stack(frames), np.stack(poses)
+    st.intrinsics, st.width, st.height = K, 97, 61
+    st.n_frames = 4
+    st.params = dict(voxel_size=0.008, mu=0.03, max_w=50, n_buckets=2 ** 12, n_excess=2 ** 10)
+    return st
 
 
 def camera_depth(P, T_wc):

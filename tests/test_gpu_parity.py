@@ -6,8 +6,9 @@ pixels (fraction bars, see gpu_util.compare_raycast)."""
 import numpy as np
 import pytest
 
-from synth import make_stream, render_depth, Scene as SynthScene, pose_look_at
-from tests.gpu_util import (compare_raycast, compare_volumes, fuse_gpu, fuse_oracle, gpu, K_of)
+from synth import make_stream
+from tests.gpu_util import (compare_raycast, compare_volumes, fuse_gpu, fuse_oracle, gpu, K_of,
+                            ragged_stream)
 
 pytestmark = pytest.mark.gpu
 
@@ -40,30 +41,7 @@ def test_vga_30_frames():
 
 def test_ragged_image_and_invalid_pixels():
     # 97 x 61 image (not a multiple of the 16x16 tile), NaN / inf / negative pixels
-    rng = np.random.default_rng(3)
-    K = (80.0, 80.0, 48.3, 30.1)
-    scene = SynthScene(spheres=np.array([[0.1, -0.05, 1.0, 0.25]]),
-                       planes=np.array([[0.0, 0.0, -1.0, -1.6]]))
-    frames, poses = [], []
-    for a in np.linspace(-0.1, 0.1, 4):
-        T = pose_look_at((a, 0.02, 0.0), (0.1, -0.05, 1.0), (0, -1, 0))
-        d = render_depth(scene, K, 97, 61, T).astype(np.float32)
-        d += (rng.standard_normal(d.shape) * 0.001).astype(np.float32)
-        bad = rng.random(d.shape)
-        d[bad < 0.02] = np.nan
-        d[(bad >= 0.02) & (bad < 0.03)] = np.inf
-        d[(bad >= 0.03) & (bad < 0.04)] = -1.0
-        d[(bad >= 0.04) & (bad < 0.05)] = 0.0
-        frames.append(d)
-        poses.append(T)
-
-    class S:  # minimal stream object
-        pass
-    st = S()
-    st.depth, st.T_wc = np.stack(frames), np.stack(poses)
-    st.intrinsics, st.width, st.height = K, 97, 61
-    st.n_frames = 4
-    st.params = dict(voxel_size=0.008, mu=0.03, max_w=50, n_buckets=2 ** 12, n_excess=2 ** 10)
+    st = ragged_stream()
     print("case: ragged 97x61 with invalid pixels", flush=True)
     g, grays, _ = fuse_gpu(st, ray_frames=(3,))
     o, orays, _ = fuse_oracle(st, ray_frames=(3,))
