@@ -2,8 +2,10 @@
 """Throughput of the per-frame fusion hot path on one MI355X.
 
 A step is one frame through the whole path: allocation, visible-list compaction,
-integration (itm_integrate) and a raycast from the frame's pose (itm_raycast), on a
-seeded synthetic VGA depth stream already resident in HBM.  Prints one JSON line.
+integration (itm_integrate) and a raycast from the frame's pose (itm_raycast)
+searching each pixel's expected depth range (section "Raycast"; --search-range off
+searches [z_near, z_far] instead), on a seeded synthetic VGA depth stream already
+resident in HBM.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps 290] [--warmup 10] [--fmt f32|f16|s16u8]
 """
@@ -122,9 +124,9 @@ def learned_leg(itm, torch, steps=20, batch=256):
             "flop_model": "algorithmic: real channels only (layer 1: 2 in, layer 4: 1 out)"}
 
 
-def cpu_baseline(stream, seconds):
+def cpu_baseline(stream, seconds, search_range):
     """The CPU oracle (allocation + integration, plain loops) on the first frames
-    of the same stream until about `seconds` of work."""
+    of the same stream until about `seconds` of work, then one raycast."""
     import oracle
     sc = oracle.Scene.from_params(stream.params)
     vox, t0, n = 0, time.perf_counter(), 0
@@ -136,11 +138,14 @@ def cpu_baseline(stream, seconds):
             break
     t_int = time.perf_counter() - t0
     t1 = time.perf_counter()
-    sc.raycast(stream.width, stream.height, stream.intrinsics, stream.T_wc[n - 1])
+    args = (stream.width, stream.height, stream.intrinsics, stream.T_wc[n - 1])
+    zr = sc.expected_depths(*args) if search_range else None
+    sc.raycast(*args, zrange=zr)
     t_rc = time.perf_counter() - t1
+    what = "expected depths + ranged raycast" if search_range else "raycast"
     return {"value": vox / t_int, "unit": "voxels/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"frames 0..{n - 1} of the same stream, allocation + integration "
-                      f"({t_int:.1f} s); raycast of frame {n - 1}: "
+                      f"({t_int:.1f} s); {what} of frame {n - 1}: "
                       f"{stream.width * stream.height / t_rc:.3g} rays/s",
             "rays_per_s": stream.width * stream.height / t_rc}
 
@@ -152,6 +157,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--fmt", default="f32", choices=sorted(SDF_BYTES))
     ap.add_argument("--workload", default="vga", choices=["vga", "large", "tiny"])
+    ap.add_argument("--search-range", default="on", choices=["on", "off"],
+                    help="raycast inside the expected depth ranges (on) or over [z_near, z_far]")
     ap.add_argument("--no-events", action="store_true", help="skip per-kernel HIP events")
     ap.add_argument("--event-every", type=int, default=10,
                     help="record per-kernel HIP events on every n-th timed frame")
@@ -190,6 +197,8 @@ def main():
     nrm = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
 
     sc = itm.Scene.from_params(st.params, fmt=args.fmt)
+    ranged = args.search_range == "on"
+    sc.set_search_range(ranged)
     for f in range(args.warmup):
         sc.integrate(depth[f], K, st.T_wc[f])
         sc.raycast(K, st.T_wc[f], pts, nrm)
@@ -264,7 +273,7 @@ def main():
                                f"{args.warmup}..{args.warmup + args.steps - 1}, voxel "
                                f"{p['voxel_size']} m, mu {p['mu']} m, 2^{int(np.log2(p['n_buckets']))} "
                                f"buckets + 2^{int(np.log2(p['n_excess']))} excess, raycast {W}x{H}",
-                   "storage": args.fmt},
+                   "storage": args.fmt, "search_range": "expected depths" if ranged else "z_near..z_far"},
         "rays_per_s": rays / wall,
         "updated_voxels_per_s": upd_total / wall,
         "visible_blocks_per_frame": vis_total / args.steps,
@@ -277,7 +286,7 @@ def main():
         out["learned"] = learned_leg(itm, torch)
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(st, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(st, args.cpu_seconds, ranged)
     sc.close()
     print(json.dumps(out), flush=True)
 

@@ -61,26 +61,32 @@ struct BlockReader {
 // any voxel of the region is read with one gather.
 template <int FMT>
 struct Cube {
-    int bx0, by0, bz0;
+    int bx0, by0, bz0;   // first block per axis
+    int bx1, by1, bz1;   // last block per axis (bx0 or bx0 + 1)
     int32_t p[8];   // block pointer of (dx, dy, dz) = (c & 1, c >> 1 & 1, c >> 2 & 1)
 
-    // the march's cached block is reused; others are probed unless the LDS block
-    // filter proves them absent
-    __device__ void fetch(const HashView &h, const BlockReader<FMT> &rd, int lx, int ly, int lz, int hx,
-                          int hy, int hz)
+    // whether every voxel of the region [l, h] lies in the blocks fetched
+    __device__ bool holds(int lx, int ly, int lz, int hx, int hy, int hz) const
+    {
+        return (lx >> 3) >= bx0 && (hx >> 3) <= bx1 && (ly >> 3) >= by0 && (hy >> 3) <= by1 &&
+               (lz >> 3) >= bz0 && (hz >> 3) <= bz1;
+    }
+
+    // every block is probed unless the LDS block filter proves it absent (the
+    // march's cached block is not reused: keeping it live costs registers)
+    __device__ void fetch(const HashView &h, const uint32_t *filt, int lx, int ly, int lz, int hx, int hy, int hz)
     {
         bx0 = lx >> 3; by0 = ly >> 3; bz0 = lz >> 3;
-        const int bx1 = hx >> 3, by1 = hy >> 3, bz1 = hz >> 3;
+        bx1 = hx >> 3; by1 = hy >> 3; bz1 = hz >> 3;
         const bool sx = bx1 != bx0, sy = by1 != by0, sz = bz1 != bz0;
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
             const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
             const int kx = dx ? bx1 : bx0, ky = dy ? by1 : by0, kz = dz ? bz1 : bz0;
-            const bool cached = kx == rd.cx && ky == rd.cy && kz == rd.cz;
             const uint32_t fi = bfilt_index(kx, ky, kz);
-            const bool maybe = (rd.filt[fi >> 5] >> (fi & 31)) & 1u;
-            p[c] = !need ? -1 : cached ? rd.cptr : maybe ? find_block_direct(h, kx, ky, kz) : -1;
+            const bool maybe = (filt[fi >> 5] >> (fi & 31)) & 1u;
+            p[c] = need && maybe ? find_block_direct(h, kx, ky, kz) : -1;
         }
     }
     __device__ float F(const typename Vox<FMT>::S *sdf, int vx, int vy, int vz) const
@@ -113,21 +119,53 @@ __device__ __forceinline__ float trilinear8(const float Fc[8], float rx, float r
     return acc;
 }
 
-// the 8 voxels of the cell of q (with the cell corner and fractions)
+// the cell with corner i and the outer layers of its 6 face neighbours: the
+// 32 voxels of the central differences of F_t at +- one voxel
 template <int FMT>
-__device__ void cell_at(const HashView &h, const BlockReader<FMT> &rd, const typename Vox<FMT>::S *sdf,
-                        float qx, float qy, float qz, int i[3], float r[3], float Fc[8])
+__device__ __forceinline__ void stencil(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int ix, int iy,
+                                        int iz, float Fc[8], float Ex[2][4], float Ey[2][4], float Ez[2][4])
 {
-    const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-    i[0] = (int)fx; i[1] = (int)fy; i[2] = (int)fz;
-    r[0] = qx - fx; r[1] = qy - fy; r[2] = qz - fz;
-    Cube<FMT> cb;
-    cb.fetch(h, rd, i[0], i[1], i[2], i[0] + 1, i[1] + 1, i[2] + 1);
-    cb.cell(sdf, i[0], i[1], i[2], Fc);
+    cb.cell(sdf, ix, iy, iz, Fc);
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int a0 = k & 1, a1 = k >> 1;
+        Ex[0][k] = cb.F(sdf, ix - 1, iy + a0, iz + a1);
+        Ex[1][k] = cb.F(sdf, ix + 2, iy + a0, iz + a1);
+        Ey[0][k] = cb.F(sdf, ix + a0, iy - 1, iz + a1);
+        Ey[1][k] = cb.F(sdf, ix + a0, iy + 2, iz + a1);
+        Ez[0][k] = cb.F(sdf, ix + a0, iy + a1, iz - 1);
+        Ez[1][k] = cb.F(sdf, ix + a0, iy + a1, iz + 2);
+    }
+}
+
+// gradient of F_t at fractions r of the cell whose 8 voxels are Fc, by central
+// differences at +- one voxel per axis (each side one trilinear interpolation,
+// sharing Fc), accumulated into g
+__device__ __forceinline__ void gradient(const float Fc[8], const float Ex[2][4], const float Ey[2][4],
+                                         const float Ez[2][4], float rx, float ry, float rz, float &gx, float &gy,
+                                         float &gz)
+{
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int a0 = k & 1, a1 = k >> 1;
+        // x pair: corners (y, z) = (a0, a1) of the cell; Fc index dx + 2 dy + 4 dz
+        const float wyz = (a0 ? ry : 1.0f - ry) * (a1 ? rz : 1.0f - rz);
+        const float xp = (1.0f - rx) * Fc[1 + 2 * a0 + 4 * a1] + rx * Ex[1][k];
+        const float xm = (1.0f - rx) * Ex[0][k] + rx * Fc[0 + 2 * a0 + 4 * a1];
+        gx = fmaf(wyz, xp - xm, gx);
+        const float wxz = (a0 ? rx : 1.0f - rx) * (a1 ? rz : 1.0f - rz);
+        const float yp = (1.0f - ry) * Fc[a0 + 2 + 4 * a1] + ry * Ey[1][k];
+        const float ym = (1.0f - ry) * Ey[0][k] + ry * Fc[a0 + 0 + 4 * a1];
+        gy = fmaf(wxz, yp - ym, gy);
+        const float wxy = (a0 ? rx : 1.0f - rx) * (a1 ? ry : 1.0f - ry);
+        const float zp = (1.0f - rz) * Fc[a0 + 2 * a1 + 4] + rz * Ez[1][k];
+        const float zm = (1.0f - rz) * Ez[0][k] + rz * Fc[a0 + 2 * a1 + 0];
+        gz = fmaf(wxy, zp - zm, gz);
+    }
 }
 
 template <int FMT>
-__global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raycast(RaycastArgs a)
 {
     const FrameGeom &g = a.fg;
     int tx, ty;
@@ -180,7 +218,8 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     // reciprocal direction for the macro-cell exit
     const float idx = 1.0f / dx, idy = 1.0f / dy, idz = 1.0f / dz;
 
-    BlockReader<FMT> rd(a.h, a.sdf, s_filt + kMacroWords);
+    const uint32_t *s_bfilt = s_filt + kMacroWords;
+    BlockReader<FMT> rd(a.h, a.sdf, s_bfilt);
     float t = t_near;
     int state = RC_COARSE, fine_miss = 0;
     for (int it = 0; it < cap && t < t_far; it++) {
@@ -209,14 +248,15 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
                 t = fmaf(m, bs, t);
                 continue;
             }
-            float F;
-            if (!rd.nearest(qx, qy, qz, F)) t += bs;
-            else { t = fmaxf(t - bs, t_near); state = RC_FINE; fine_miss = 0; }
-            continue;
         }
+        // one sample site for every state, so that a wave whose lanes are in
+        // different states runs the hash probe once
         float F;
         const bool found = rd.nearest(qx, qy, qz, F);
-        if (state == RC_FINE) {
+        if (state == RC_COARSE) {
+            if (!found) t += bs;
+            else { t = fmaxf(t - bs, t_near); state = RC_FINE; fine_miss = 0; }
+        } else if (state == RC_FINE) {
             if (!found) {
                 t += mu;
                 if (++fine_miss > fine_budget) state = RC_COARSE;
@@ -234,54 +274,59 @@ __global__ __launch_bounds__(256) void k_raycast(RaycastArgs a)
     float4 P = make_float4(0.f, 0.f, 0.f, 0.f), N = make_float4(0.f, 0.f, 0.f, 0.f);
     if (state == RC_BEHIND) {
         const auto *sdf = (const typename Vox<FMT>::S *)a.sdf;
-        int ci[3];
-        float cr[3], Fc[8];
-#pragma unroll
-        for (int k = 0; k < 2; k++) {
-            cell_at<FMT>(a.h, rd, sdf, fmaf(t, dx, ox), fmaf(t, dy, oy), fmaf(t, dz, oz), ci, cr, Fc);
-            t = fmaf(trilinear8(Fc, cr[0], cr[1], cr[2]), mu, t);
-        }
-        const float qx = fmaf(t, dx, ox), qy = fmaf(t, dy, oy), qz = fmaf(t, dz, oz);
-        P = make_float4((float)(g.twc[0] + (double)t * dir[0]), (float)(g.twc[1] + (double)t * dir[1]),
-                        (float)(g.twc[2] + (double)t * dir[2]), 1.0f);
-        // normal: central differences of F_t at q +- one voxel per axis.  They read
-        // the cell of q (usually the second refinement's cell, already loaded) and
-        // its 6 face neighbours' outer layers, 24 more voxels in one batch.
-        const float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
-        const int ix = (int)fx, iy = (int)fy, iz = (int)fz;
-        const float rx = qx - fx, ry = qy - fy, rz = qz - fz;
+        // One block neighbourhood for the whole final phase: the blocks of voxels
+        // [i - 3, i + 4] per axis around the first refinement cell i (at most
+        // 2 x 2 x 2 blocks, probed together) hold both refinement cells and the
+        // normal's stencil unless the second step moves more than 2 voxels.
+        float qx = fmaf(t, dx, ox), qy = fmaf(t, dy, oy), qz = fmaf(t, dz, oz);
+        float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
+        int ix = (int)fx, iy = (int)fy, iz = (int)fz;
         Cube<FMT> cb;
-        cb.fetch(a.h, rd, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
-        if (ix != ci[0] || iy != ci[1] || iz != ci[2]) cb.cell(sdf, ix, iy, iz, Fc);
-        float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int a0 = k & 1, a1 = k >> 1;
-            Ex[0][k] = cb.F(sdf, ix - 1, iy + a0, iz + a1);
-            Ex[1][k] = cb.F(sdf, ix + 2, iy + a0, iz + a1);
-            Ey[0][k] = cb.F(sdf, ix + a0, iy - 1, iz + a1);
-            Ey[1][k] = cb.F(sdf, ix + a0, iy + 2, iz + a1);
-            Ez[0][k] = cb.F(sdf, ix + a0, iy + a1, iz - 1);
-            Ez[1][k] = cb.F(sdf, ix + a0, iy + a1, iz + 2);
-        }
+        cb.fetch(a.h, s_bfilt, ix - 3, iy - 3, iz - 3, ix + 4, iy + 4, iz + 4);
+        float Fc[8];
+        cb.cell(sdf, ix, iy, iz, Fc);
+        t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
+        // Second refinement: its cell and, speculatively, the normal stencil
+        // around it.  The final point nearly always stays in that cell; when it
+        // moves to a neighbouring cell, a second pass loads that cell's stencil.
+        // The neighbourhood is widened first to hold the stencils of the cell and
+        // of its 26 neighbours, so that no probe happens inside the loop; only the
+        // gradient leaves it.  (A final point farther away still gets the exact
+        // stencil, after the loop.)
+        qx = fmaf(t, dx, ox); qy = fmaf(t, dy, oy); qz = fmaf(t, dz, oz);
+        fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
+        ix = (int)fx; iy = (int)fy; iz = (int)fz;
+        if (!cb.holds(ix - 2, iy - 2, iz - 2, ix + 3, iy + 3, iz + 3))
+            cb.fetch(a.h, s_bfilt, ix - 2, iy - 2, iz - 2, ix + 3, iy + 3, iz + 3);
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const int a0 = k & 1, a1 = k >> 1;
-            // x pair: corners (y, z) = (iy + a0, iz + a1); Fc index dx + 2 dy + 4 dz
-            const float wyz = (a0 ? ry : 1.0f - ry) * (a1 ? rz : 1.0f - rz);
-            const float xp = (1.0f - rx) * Fc[1 + 2 * a0 + 4 * a1] + rx * Ex[1][k];
-            const float xm = (1.0f - rx) * Ex[0][k] + rx * Fc[0 + 2 * a0 + 4 * a1];
-            gx = fmaf(wyz, xp - xm, gx);
-            const float wxz = (a0 ? rx : 1.0f - rx) * (a1 ? rz : 1.0f - rz);
-            const float yp = (1.0f - ry) * Fc[a0 + 2 + 4 * a1] + ry * Ey[1][k];
-            const float ym = (1.0f - ry) * Ey[0][k] + ry * Fc[a0 + 0 + 4 * a1];
-            gy = fmaf(wxz, yp - ym, gy);
-            const float wxy = (a0 ? rx : 1.0f - rx) * (a1 ? ry : 1.0f - ry);
-            const float zp = (1.0f - rz) * Fc[a0 + 2 * a1 + 4] + rz * Ez[1][k];
-            const float zm = (1.0f - rz) * Ez[0][k] + rz * Fc[a0 + 2 * a1 + 0];
-            gz = fmaf(wxy, zp - zm, gz);
+        bool done = false;
+        for (int pass = 0; pass < 2; pass++) {
+            if (pass == 1) {
+                fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
+                ix = (int)fx; iy = (int)fy; iz = (int)fz;
+                if (!cb.holds(ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2)) break;
+            }
+            float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
+            stencil(cb, sdf, ix, iy, iz, Fc, Ex, Ey, Ez);
+            if (pass == 0) {
+                t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
+                qx = fmaf(t, dx, ox); qy = fmaf(t, dy, oy); qz = fmaf(t, dz, oz);
+                if (floorf(qx) != fx || floorf(qy) != fy || floorf(qz) != fz) continue;
+            }
+            gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
+            done = true;
+            break;
         }
+        if (!done) {   // the final point left the neighbourhood (rare)
+            cb.fetch(a.h, s_bfilt, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
+            float Ex[2][4], Ey[2][4], Ez[2][4];
+            stencil(cb, sdf, ix, iy, iz, Fc, Ex, Ey, Ez);
+            gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
+        }
+        // the hit in metres, (o + t d) s in binary64 from the march's binary32 terms
+        P = make_float4((float)(g.s * ((double)ox + (double)t * (double)dx)),
+                        (float)(g.s * ((double)oy + (double)t * (double)dy)),
+                        (float)(g.s * ((double)oz + (double)t * (double)dz)), 1.0f);
         const float n2 = gx * gx + gy * gy + gz * gz;
         if (n2 > 0.0f) {
             const float r = 1.0f / sqrtf(n2);
