@@ -42,10 +42,10 @@ TRAFFIC_KIB = {}
 
 def kernel_source_sha(name):
     import hashlib
-    files = {"alloc": "itm_alloc.hip", "integrate": "itm_integrate.hip", "raycast": "itm_raycast.hip",
-             "refine": "itm_refine.hip"}[name]
+    files = {"alloc": ("itm_integrate.hip", "itm_alloc.hpp"), "integrate": ("itm_integrate.hip", "itm_alloc.hpp"),
+             "raycast": ("itm_raycast.hip",), "refine": ("itm_refine.hip",)}[name]
     h = hashlib.sha256()
-    for f in (files, "itm_internal.hpp"):
+    for f in files + ("itm_internal.hpp",):
         with open(os.path.join(ROOT, "paper_1410_0925_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -67,13 +67,13 @@ def kernel_bytes(name, fmt, W, H, launches, vis_total, upd_total, n_entries):
     if launches == 0:
         return 0.0
     vis = vis_total / launches
-    if name == "integrate":
-        # read + write F and W of every updated voxel; scan every visibility flag
-        # and clear the set ones (the visible-list stage fused in)
-        return 2.0 * VOX_BYTES[fmt] * upd_total / launches + float(n_entries) + vis
     if name == "alloc":
-        # the depth image + one 32-byte bucket record per visible block + flags
-        return 4.0 * W * H + 32.0 * vis + vis
+        # the depth image; per visible block its 16-byte bucket record, its
+        # 4-byte visibility stamp and its 16-byte list record
+        return 4.0 * W * H + vis * (16.0 + 4.0 + 16.0)
+    if name == "integrate":
+        # the list records; read + write F and W of every updated voxel
+        return 16.0 * vis + 2.0 * VOX_BYTES[fmt] * upd_total / launches
     if name == "raycast":
         # two float4 maps out + the F values of the blocks in view (estimated by
         # the frame's visible blocks) + one bucket record each

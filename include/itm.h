@@ -174,8 +174,10 @@ itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
 
 /* Per-kernel timing with HIP events recorded on the scene's stream around every
  * launch while enabled (toggling does not synchronise; events recorded while
- * enabled are kept until read).  Kernel ids: 0 allocation, 1 visible-list
- * compaction fused with integration, 2 raycast, 3 refiner gate. */
+ * enabled are kept until read).  Kernel ids: 0 allocation with the visible
+ * list (and, with the search range on, the expected-depth binning), 1
+ * integration, 2 raycast (with the binning for a pose other than the last
+ * frame's), 3 refiner gate. */
 #define ITM_KERNEL_COUNT 4
 itm_status itm_profile_enable(itm_scene *scene, int enable);
 /* Synchronises, then writes the summed milliseconds and launch counts per kernel

@@ -1,10 +1,10 @@
 // Integration (section "Integration", computeUpdatedVoxelDepthInfo) over the
 // voxels of the frame's visible blocks.
 //
-// One wave per visible block (the workgroups find their blocks by scanning the
-// visibility flags, so no count is read back).  Lane l owns voxels 4l..4l+3 and
-// 256+4l..256+4l+3 of the block,
-// so every voxel load or store instruction of a wave covers one contiguous range
+// One wave per visible block, taken from the visible list the allocation built
+// (its counters are read on the device: no count goes to the host).  Lane l
+// owns voxels 4l..4l+3 and 256+4l..256+4l+3 of the block, so every voxel load
+// or store instruction of a wave covers one contiguous range
 // (16 B per lane in the float form).  A lane reads its 8 voxels, decides for
 // each whether it is updated -- that needs only the voxel's position and the
 // depth image -- and writes back a group of 4 voxels only when one of them is.
@@ -14,7 +14,7 @@
 // once per block and split into a binary32 pair hi + lo; the in-block offset
 // (lx g_x + ly g_y) + lz g_z is added to lo first.  The value eta = d - p_z is
 // formed as (d - hi_z) - (lo_z + offset_z), accurate to ~1e-8 m at room scale.
-#include "itm_internal.hpp"
+#include "itm_alloc.hpp"
 
 namespace itm {
 
@@ -103,14 +103,10 @@ struct Group4<ITM_VOX_S16U8> {
 
 // one visible block (entry e) by one wave; returns the lane's updated voxels
 template <int FMT>
-__device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane, unsigned long long &key_out)
+__device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, int32_t e, int lane)
 {
     const FrameGeom &g = a.fg;
-    unsigned long long key;
-    int32_t ptr;
-    entry_at(a.h, e, key, ptr);
-    key_out = key;
-    if (ptr < 0) return 0;  // cannot happen: every flagged entry owns a block
+    const int32_t ptr = e;   // the entry's voxel block
     int kx, ky, kz;
     unpack_key(key, kx, ky, kz);
     // block origin in camera coordinates, binary64 -> binary32 pair
@@ -184,90 +180,76 @@ __device__ uint32_t integrate_block(const IntegrateArgs &a, int32_t e, int lane,
     return n_upd;
 }
 
-constexpr int kScanThreads = 256;
-constexpr int kScanEntries = kScanThreads * 8;   // flag bytes per workgroup
-static_assert(kScanEntries == kSegEntries, "one visible-list segment per workgroup");
-
-// Expected-depth rectangles of the workgroup's n visible blocks at the frame's
-// pose, appended to the bins of the tiles they overlap.  8 lanes per block take
-// its 8 box corners and merge them with a butterfly; 32 blocks per pass.  A
-// phase of its own after the integration, so that its binary64 temporaries do
-// not add to the integration's registers.
-__device__ void bin_blocks(const IntegrateArgs &a, const unsigned long long *keys, int n)
+// The per-frame kernel: allocation and visible list (itm_alloc.hpp) and the
+// integration of the blocks the workgroup owns.
+//   1. housekeeping, every workgroup its share: the previous frame's claim slots
+//      and, with the search range on, the next frame's bin counts are cleared;
+//   2. each thread walks its pixel's band segment, finds or inserts the blocks,
+//      and records them in the workgroup's LDS set;
+//   3. every block of the set is stamped with the frame number; the workgroup
+//      that stamps a block first owns it: it appends it to the visible list and
+//      integrates it -- one wave per block -- so each visible block is
+//      integrated exactly once, by a workgroup that has just touched its bucket;
+//   4. with the search range on, the owned blocks' expected-depth rectangles are
+//      binned by image tile.
+// The list append's atomic is issued before the integration and its result used
+// after it, so its round trip overlaps the voxel work.
+// Allocation and visible list (itm_alloc.hpp), one thread per pixel:
+//   1. housekeeping, every workgroup its share: the previous frame's claim slots
+//      and, with the search range on, the next frame's bin counts are cleared;
+//   2. each thread walks its pixel's band segment, finds or inserts the blocks,
+//      and records them in the workgroup's LDS set;
+//   3. every block of the set is stamped with the frame number; the workgroup
+//      that stamps a block first lists it (one atomic per workgroup on one of 32
+//      list stripes), so each visible block is listed exactly once;
+//   4. with the search range on, the listed blocks' expected-depth rectangles
+//      are binned by image tile.
+__global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
 {
     const FrameGeom &g = a.fg;
-    const int grp = threadIdx.x >> 3, corner = threadIdx.x & 7;
-    for (int base = 0; base < n; base += kScanThreads / 8) {   // uniform
-        const int j = base + grp;
-        BoxAcc b;
-        if (j < n) {
-            int kx, ky, kz;
-            unpack_key(keys[j], kx, ky, kz);
-            box_corner(g, kx, ky, kz, corner, b);
-        } else {
-            b.zlo = b.xlo = b.ylo = INFINITY;
-            b.zhi = b.xhi = b.yhi = -INFINITY;
-            b.behind = false;
+    __shared__ int32_t s_e[kSet];
+    __shared__ unsigned long long s_k[kSet];
+    __shared__ int s_wave[4], s_n, s_base, s_ovf;
+    // 1. housekeeping
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < kStripes) {
+            a.cnt->upd[a.parity ^ 1][threadIdx.x][0] = 0;
+            a.cnt->vis[a.parity ^ 1][threadIdx.x][0] = 0;
         }
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-            BoxAcc c;
-            c.zlo = __shfl_xor(b.zlo, o, kWave);
-            c.zhi = __shfl_xor(b.zhi, o, kWave);
-            c.xlo = __shfl_xor(b.xlo, o, kWave);
-            c.xhi = __shfl_xor(b.xhi, o, kWave);
-            c.ylo = __shfl_xor(b.ylo, o, kWave);
-            c.yhi = __shfl_xor(b.yhi, o, kWave);
-            c.behind = __shfl_xor((int)b.behind, o, kWave) != 0;
-            box_merge(b, c);
-        }
-        RangeRect r;
-        if (j < n && box_rect(g, b, r)) {
-            int tx0, ty0, ntx, n_tiles;
-            rect_tiles(r, tx0, ty0, ntx, n_tiles);
-            for (int t = corner; t < n_tiles; t += 8) {
-                const int tile = (ty0 + t / ntx) * a.rb.tw + tx0 + t % ntx;
-                const int slot = atomicAdd(&a.rb.cnt[tile], 1);
-                if (slot < a.rb.cap) a.rb.rect[(int64_t)tile * a.rb.cap + slot] = r;
-            }
-        }
+        if (threadIdx.x < kListSegs) a.list_clear[32 * threadIdx.x] = 0;
+        if (threadIdx.x == 0) *a.set_used_next = 0;
     }
-}
-
-__device__ __forceinline__ int bytes_set(uint32_t x) { return (int)((x * 0x01010101u) >> 24); }
-
-
-// Stage three of the allocation (the visible list) fused with the integration:
-// workgroup b scans flag bytes [2048 b, 2048 b + 2048), clears them, compacts
-// the set ones into an LDS list (wave prefix sums) -- also written out as
-// segment b of the visible list -- and its 4 waves integrate those blocks.  The hash spreads blocks uniformly over the entries, so every
-// workgroup gets about the same share (about 4 blocks at VGA).  The same pass
-// clears the allocation's claim-set slots.
-template <int FMT>
-__global__ __launch_bounds__(kScanThreads) void k_integrate(IntegrateArgs a)
-{
-    __shared__ int32_t s_list[kScanEntries];
-    __shared__ unsigned long long s_key[kScanEntries];   // block keys, for the range bins
-    __shared__ int s_wave[kScanThreads / kWave];
-    __shared__ int s_n;
-    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-    const int nwaves = kScanThreads / kWave;
-    // scan and clear 8 flags per thread
-    const int64_t w8 = (int64_t)blockIdx.x * kScanThreads + threadIdx.x;
-    uint2 f = make_uint2(0u, 0u);
-    if (w8 < a.n_words8) f = a.vis8[w8];
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.cnt->set_used[a.parity ^ 1] = 0;  // next frame's counter
     {
-        const int su = a.cnt->set_used[a.parity];
-        for (int i = blockIdx.x * kScanThreads + threadIdx.x; i < su; i += gridDim.x * kScanThreads)
-            a.set[a.set_list[i]] = 0ull;
+        const int gt = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
+        const int su = *a.set_used_prev;
+        for (int i = gt; i < su; i += gs) a.set_prev[a.set_list_prev[i]] = 0ull;
+        if (a.rb.cnt)
+            for (int i = gt; i < a.n_clear; i += gs) a.rb_clear[i] = 0;
     }
-    if (a.rb.cnt) {   // the next frame's bins
-        for (int i = blockIdx.x * kScanThreads + threadIdx.x; i < a.n_clear; i += gridDim.x * kScanThreads)
-            a.rb_clear[i] = 0;
+    int tx, ty;
+    if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;   // whole workgroup
+#pragma unroll
+    for (int j = 0; j < kSet / 256; j++) s_e[threadIdx.x + 256 * j] = -1;
+    __syncthreads();
+    // 2. allocation
+    {
+        const int u = tx * 16 + (threadIdx.x & 15);
+        const int v = ty * 16 + (threadIdx.x >> 4);
+        if (u < g.W && v < g.H) {
+            const float depth = a.depth[(int64_t)v * g.W + u];
+            if (depth > 0.0f && !isinf(depth)) alloc_pixel(a, u, v, depth, s_e, s_k);
+        }
     }
-    const int c = bytes_set(f.x) + bytes_set(f.y);
-    if (c) a.vis8[w8] = make_uint2(0u, 0u);
+    __syncthreads();
+    // 3. the visible list: thread t stamps set slots 8t..8t+7
+    uint32_t win = 0;
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        const int32_t e = s_e[8 * threadIdx.x + j];
+        if (e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) win |= 1u << j;
+    }
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int c = __builtin_popcount(win);
     int incl = c;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -275,68 +257,117 @@ __global__ __launch_bounds__(kScanThreads) void k_integrate(IntegrateArgs a)
         if (lane >= o) incl += y;
     }
     if (lane == kWave - 1) s_wave[wave] = incl;
+    unsigned long long wkey[8];
+    int32_t went[8];
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        wkey[j] = s_k[8 * threadIdx.x + j];
+        went[j] = s_e[8 * threadIdx.x + j];
+    }
     __syncthreads();
+    const int stripe = blockIdx.x % 32;
     if (threadIdx.x == 0) {
         int t = 0;
-        for (int w = 0; w < nwaves; w++) {
+        for (int w = 0; w < 4; w++) {
             const int x = s_wave[w];
             s_wave[w] = t;
             t += x;
         }
-        s_n = t;
-        a.seg.cnt[blockIdx.x] = t;
+        int base = 0, ovf = 0;
         if (t) {
-            const int sI = blockIdx.x % kStripes;
-            atomicAdd(&a.cnt->vis[0][sI][0], (unsigned long long)t);
-            atomicAdd(&a.cnt->vis[1][sI][0], (unsigned long long)t);
+            base = atomicAdd(&a.list.cnt[32 * stripe], t);
+            // records past the stripe's capacity go to the overflow segment
+            const int spill = min(t, max(0, base + t - a.list.cap));
+            if (spill) ovf = atomicAdd(&a.list.cnt[32 * 32], spill);
+        }
+        s_n = t;
+        s_base = base;
+        s_ovf = ovf;
+    }
+    __syncthreads();
+    const int n_won = s_n, base = s_base, ovf = s_ovf;
+    int k = s_wave[wave] + incl - c;   // workgroup index of this thread's first record
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        if (!(win & (1u << j))) continue;
+        VisRec r;
+        r.key = wkey[j];
+        r.e = went[j];
+        r.pad = 0;
+        const int pos = base + k;   // stripe position
+        const int64_t slot = pos < a.list.cap ? (int64_t)stripe * a.list.cap + pos
+                                              : (int64_t)32 * a.list.cap + ovf + (pos - max(base, a.list.cap));
+        a.list.rec[slot] = r;
+        s_k[k] = wkey[j];   // the won keys, in list order, for the binning
+        k++;
+    }
+    // 4. expected-depth rectangles
+    if (!a.rb.cnt || n_won == 0) return;   // uniform
+    __syncthreads();
+    bin_blocks(g, a.rb, s_k, n_won);
+}
+
+// Integration: one wave per visible block.  Wave gw serves list stripe
+// gw % 32, items gw / 32, gw / 32 + nw / 32, ... (the grid is a multiple of 8
+// workgroups), then the overflow segment.  The record is loaded together with
+// the stripe's counter -- it lies inside the stripe's storage whatever the
+// count -- so the two take one memory round instead of two.
+template <int FMT>
+__global__ __launch_bounds__(256) void k_integrate(FuseArgs a)
+{
+    __shared__ unsigned long long s_red[2][4];
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    const int gw = blockIdx.x * 4 + wave, nw = gridDim.x * 4;
+    const int stripe = gw & 31, step = nw >> 5;
+    uint32_t n_upd = 0, n_blk = 0;
+    {
+        const int n = a.list.cnt[32 * stripe];
+        for (int i = gw >> 5; i < a.list.cap; i += step) {   // uniform over the wave
+            const VisRec r = a.list.rec[(int64_t)stripe * a.list.cap + i];
+            if (i >= n) break;
+            n_upd += integrate_block<FMT>(a, r.key, r.e, lane);
+            n_blk++;
         }
     }
-    __syncthreads();
-    if (c) {
-        int k = s_wave[wave] + incl - c;
-        int32_t *seg = a.seg.list + (int64_t)blockIdx.x * kSegEntries;
-        const uint32_t w2[2] = {f.x, f.y};
-#pragma unroll
-        for (int q = 0; q < 8; q++)
-            if ((w2[q >> 2] >> (8 * (q & 3))) & 0xffu) {
-                const int32_t e = (int32_t)(w8 * 8 + q);
-                s_list[k] = e;
-                seg[k] = e;
-                k++;
-            }
-    }
-    __syncthreads();
-    const int n = s_n;
-    uint32_t n_upd = 0;
-    for (int j = wave; j < n; j += nwaves) {
-        unsigned long long key;
-        n_upd += integrate_block<FMT>(a, s_list[j], lane, key);
-        if (a.rb.cnt && lane == 0) s_key[j] = key;
-    }
-    if (a.rb.cnt) {
-        __syncthreads();
-        bin_blocks(a, s_key, n);
+    {   // the overflow segment (records of full stripes)
+        const int n = a.list.cnt[32 * 32];
+        for (int i = gw; i < n; i += nw) {
+            const VisRec r = a.list.rec[(int64_t)32 * a.list.cap + i];
+            n_upd += integrate_block<FMT>(a, r.key, r.e, lane);
+            n_blk++;
+        }
     }
     // one counter update per workgroup, on one of kStripes separate lines
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) n_upd += __shfl_xor(n_upd, o, kWave);
-    __syncthreads();
-    if (lane == 0) s_wave[wave] = (int)n_upd;
+    if (lane == 0) {
+        s_red[0][wave] = n_upd;
+        s_red[1][wave] = n_blk;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int w = 0; w < nwaves; w++) t += (unsigned)s_wave[w];
-        if (t) {
-            const int sI = blockIdx.x % kStripes;
-            atomicAdd(&a.cnt->upd[0][sI][0], t);
-            atomicAdd(&a.cnt->upd[1][sI][0], t);
+        const unsigned long long u = s_red[0][0] + s_red[0][1] + s_red[0][2] + s_red[0][3];
+        const unsigned long long v = s_red[1][0] + s_red[1][1] + s_red[1][2] + s_red[1][3];
+        const int sI = blockIdx.x % kStripes;
+        if (u) {
+            atomicAdd(&a.cnt->upd[a.parity][sI][0], u);
+            atomicAdd(&a.cnt->upd[2][sI][0], u);
+        }
+        if (v) {
+            atomicAdd(&a.cnt->vis[a.parity][sI][0], v);
+            atomicAdd(&a.cnt->vis[2][sI][0], v);
         }
     }
 }
 
-hipError_t launch_integrate(int fmt, const IntegrateArgs &a, hipStream_t st)
+hipError_t launch_alloc(const FuseArgs &a, hipStream_t st)
 {
-    const int grid = (int)((a.n_words8 + kScanThreads - 1) / kScanThreads);
+    k_alloc<<<xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16)), 256, 0, st>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_integrate(int fmt, const FuseArgs &a, int grid, hipStream_t st)
+{
     switch (fmt) {
     case ITM_VOX_F32: k_integrate<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
     case ITM_VOX_F16: k_integrate<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;

@@ -1,22 +1,28 @@
 // Internal device-side definitions shared by the library's kernels.
 //
 // HBM layout of a scene (one allocation each):
-//   buckets  n_buckets x 32 B   {key[2] (u64), ptr[2] (i32), head (i32), pad}
-//            the ordered part of the hash table, 2 entries per bucket; `head` is the
-//            first excess entry of the bucket's chain (-1 = none), i.e. the offset
-//            the paper keeps in the bucket's last entry
-//   excess   n_excess x 16 B    {key (u64), ptr (i32), next (i32)}  unordered part
-//   vis      n_entries bytes    per-entry visibility flag of the current frame
-//   vis_list n_entries x i32    the frame's visible entry ids, one segment per
-//                               2048 entries: segment b holds the ids flagged in
-//                               entries [2048 b, 2048 b + 2048), compacted to its
-//                               front; seg_cnt[b] says how many
+//   buckets  n_buckets x 16 B   {key[2] (u64)} the ordered part of the hash table,
+//                               2 entries per bucket: one 16-byte load probes both
+//   head     n_buckets x i32    first excess entry of the bucket's chain (-1 =
+//                               none), i.e. the offset the paper keeps in the
+//                               bucket's last entry
+//   excess   n_excess x 16 B    {key (u64), next (i32), pad}  unordered part
+//   stamp    n_entries x u32    frame (+1) in which the entry was last listed visible
+//   vis_list (32 cap + n_entries) x 16 B   the frame's visible blocks {key, entry}:
+//                               32 stripes of `cap` records, appended to by the
+//                               allocation's workgroups (stripe = workgroup % 32),
+//                               and an overflow segment for full stripes
 //   bins     3 x n_tiles x (4 B + cap x 16 B)   expected-depth rectangles binned
 //                               by 16 x 16 pixel tile (two frame parities + one
 //                               for raycasts at another pose)
-//   sdf, w   capacity x 512     voxel block array, structure of arrays, one
-//                               element type per storage form
-//   set      R x u64            per-frame set of blocks claimed for the excess list
+//   sdf, w   n_entries x 512    voxel block array, structure of arrays, one
+//                               element type per storage form.  The array has a
+//                               block for every hash entry, so the paper's
+//                               pointer into it is the entry id itself: a probe
+//                               that finds the key has the block, with no second
+//                               load and no free-list pop on insertion
+//   set      2 x R x u64        per-frame sets of blocks claimed for the excess list
+//                               (alternating by frame)
 //   cnt      Counters           device counters
 // Entry ids follow the paper's layout: 2 b + i for slot i of bucket b, then
 // 2 n_buckets + x for excess entry x.
@@ -36,38 +42,40 @@ constexpr unsigned long long kKeyValid = 1ull << 63;
 constexpr int kWave = 64;
 constexpr int kStripes = 32;
 
-struct alignas(32) Bucket {
-    unsigned long long key[2];
-    int32_t ptr[2];
-    int32_t head;
-    int32_t pad;
+struct alignas(16) Bucket {
+    unsigned long long key[2];   // 0 = empty slot
 };
-static_assert(sizeof(Bucket) == 32, "bucket record is 32 bytes");
+static_assert(sizeof(Bucket) == 16, "bucket record is 16 bytes");
 
 struct alignas(16) Excess {
     unsigned long long key;
-    int32_t ptr;
     int32_t next;
+    int32_t pad;
 };
 static_assert(sizeof(Excess) == 16, "excess record is 16 bytes");
 
 struct Counters {
-    int32_t vba_next;       // voxel blocks handed out (bump allocator = free stack pop)
+    int32_t vba_next;       // voxel blocks allocated (a count: block = entry id)
     int32_t excess_next;    // excess entries handed out (may run past n_excess)
     int32_t pad0;
-    int32_t set_used[2];    // claim-set slots used, by frame parity
-    int32_t pad;
+    int32_t set_used[3];    // claim-set slots used, by frame % 3
     unsigned long long dropped_total;
     unsigned long long pad2[5];
     // counts striped over separate 128-byte lines so that the per-workgroup
-    // additions do not all hit one address: [frame][stripe] for the current
-    // frame (cleared by k_alloc), [total][stripe] since creation
-    unsigned long long upd[2][kStripes][16];   // updated voxels
-    unsigned long long vis[2][kStripes][16];   // visible blocks
+    // additions do not all hit one address: [frame parity][stripe] for a frame,
+    // [2][stripe] since creation.  A frame's kernel adds to its parity's counters
+    // and clears the other parity's: a counter is never both stored to and added
+    // to in one kernel (a plain store, written back from one XCD's L2 at the
+    // kernel's end, is not ordered with other XCDs' device-scope atomics)
+    unsigned long long upd[3][kStripes][16];   // updated voxels
+    unsigned long long vis[3][kStripes][16];   // visible blocks
+    // records appended to the visible list, [frame parity][segment], one line each
+    int32_t lst[2][33][32];
 };
 
 struct HashView {
     Bucket *buckets;
+    int32_t *head;
     Excess *excess;
     uint32_t *occ;      // one bit per bucket: set once the bucket holds a block
     uint32_t *macro;    // kMacroBits bits, one per hashed macro cell (4^3 blocks): set
@@ -105,27 +113,32 @@ __device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mas
     return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u)) & mask;
 }
 
-// Read-only retrieval (section "Hash Table Operations"): the bucket's two
-// entries, then the excess chain.  Returns the voxel block pointer or -1.
-__device__ __forceinline__ int32_t find_block(const HashView &h, int x, int y, int z)
+// the bucket's two entries, then (both taken) the excess chain; returns the
+// entry id, which is also the block's place in the voxel block array, or -1
+__device__ __forceinline__ int32_t probe_bucket(const HashView &h, uint32_t b, unsigned long long key)
 {
-    if (!in_key_range(x, y, z)) return -1;
-    const unsigned long long key = pack_key(x, y, z);
-    const uint32_t b = hash_index(x, y, z, h.mask);
-    // an empty bucket holds no block (the bitmap is small enough to stay in L2)
-    if (!((h.occ[b >> 5] >> (b & 31)) & 1u)) return -1;
-    const Bucket *B = h.buckets + b;
-    const ulonglong2 keys = *reinterpret_cast<const ulonglong2 *>(B->key);
-    const int4 rest = *reinterpret_cast<const int4 *>(&B->ptr[0]);  // ptr0, ptr1, head, pad
-    if (keys.x == key) return rest.x;
-    if (keys.y == key) return rest.y;
-    int32_t x_i = rest.z;
+    const ulonglong2 keys = *reinterpret_cast<const ulonglong2 *>(h.buckets[b].key);
+    if (keys.x == key) return 2 * (int32_t)b;
+    if (keys.y == key) return 2 * (int32_t)b + 1;
+    if (keys.y == 0ull) return -1;   // a free slot: the bucket has no chain
+    int32_t x_i = h.head[b];
     while (x_i >= 0) {
         const Excess E = h.excess[x_i];
-        if (E.key == key) return E.ptr;
+        if (E.key == key) return 2 * h.n_buckets + x_i;
         x_i = E.next;
     }
     return -1;
+}
+
+// Read-only retrieval (section "Hash Table Operations"): the bucket's two
+// entries, then the excess chain.  Returns the block (entry id) or -1.
+__device__ __forceinline__ int32_t find_block(const HashView &h, int x, int y, int z)
+{
+    if (!in_key_range(x, y, z)) return -1;
+    const uint32_t b = hash_index(x, y, z, h.mask);
+    // an empty bucket holds no block (the bitmap is small enough to stay in L2)
+    if (!((h.occ[b >> 5] >> (b & 31)) & 1u)) return -1;
+    return probe_bucket(h, b, pack_key(x, y, z));
 }
 
 // ---------------------------------------------------------------------------
@@ -190,25 +203,22 @@ struct FrameGeom {
     float z_near, z_far;
 };
 
-struct AllocArgs {
-    FrameGeom fg;
-    const float *depth;
-    HashView h;
-    uint8_t *vis;
-    unsigned long long *set;
-    int32_t *set_list;
-    uint32_t set_mask;
-    int32_t parity;         // frame parity: which claim counter to use
-    Counters *cnt;
-};
 
-// The visible list in segments (see the layout above); written by the
-// integration kernel, read by the refiner gate and the expected-depth binning.
-constexpr int kSegEntries = 2048;
-struct VisSegments {
-    int32_t *list;        // [n_seg][kSegEntries]
-    int32_t *cnt;         // [n_seg]
-    int32_t n_seg;
+// The frame's visible list (section "Allocation", stage three): built by the
+// allocation kernel, read by the integration, the refiner gate and the
+// expected-depth binning.  Segment s < 32 is stripe s (capacity cap), segment 32
+// the overflow (capacity n_entries); a stripe's counter may run past cap, the
+// records beyond it having gone to the overflow.
+constexpr int kListSegs = 33;
+struct alignas(16) VisRec {
+    unsigned long long key;
+    int32_t e;            // entry id = voxel block
+    int32_t pad;
+};
+struct VisList {
+    VisRec *rec;          // segment s at rec + s * cap
+    int32_t *cnt;         // segment s's counter at cnt[32 * s]
+    int32_t cap;
 };
 
 // Expected depth ranges (section "Raycast", search range).  Each visible block's
@@ -230,18 +240,30 @@ struct RangeBins {
     int32_t tw, th;       // tiles per row, per column
 };
 
-struct IntegrateArgs {
+// the per-frame kernels: allocation and visible list (and the expected-depth
+// binning at the frame's pose), then integration of the listed blocks
+struct FuseArgs {
     FrameGeom fg;
     const float *depth;
     HashView h;
-    uint2 *vis8;              // visibility flags, 8 entries per word (cleared here)
-    int64_t n_words8;
-    unsigned long long *set;  // claim set of the allocation (cleared here)
-    const int32_t *set_list;
-    int32_t parity;           // frame parity: which claim counter this frame used
-    VisSegments seg;          // the visible list, written here
-    RangeBins rb;             // rb.cnt non-null: bin this frame's rectangles (pose of the frame)
-    int32_t *rb_clear;        // counts of the other parity, cleared here (with rb)
+    int32_t parity;               // frame parity: per-frame counters and list counters
+    uint32_t *stamp;              // per entry: frame (+1) in which it was last listed
+    uint32_t stamp_now;           // this frame's value
+    // claim set of the excess insertions: this frame's table, slot list and count;
+    // the previous frame's table is cleared here (slots listed in its list), and
+    // the next frame's count zeroed (tables alternate by frame, lists by frame % 3)
+    unsigned long long *set;
+    int32_t *set_list;
+    int32_t *set_used;
+    uint32_t set_mask;
+    unsigned long long *set_prev;
+    const int32_t *set_list_prev;
+    const int32_t *set_used_prev;
+    int32_t *set_used_next;
+    VisList list;                 // this frame's visible list (appended here)
+    int32_t *list_clear;          // the other parity's list counters, cleared here
+    RangeBins rb;                 // rb.cnt non-null: bin the visible blocks' rectangles at this pose
+    int32_t *rb_clear;            // bin counts of the other parity, cleared here (with rb)
     int32_t n_clear;
     void *sdf;
     void *w;
@@ -255,7 +277,7 @@ struct RaycastArgs {
     float4 *pts;
     float4 *nrm;
     RangeBins rb;             // rb.cnt non-null: search each ray inside its expected range
-    VisSegments seg;          // for tiles whose bin overflowed
+    VisList list;             // for tiles whose bin overflowed
 };
 
 // learned refiner (itm_refine.hip)
@@ -282,7 +304,7 @@ struct RefineArgs {
 struct RefineGateArgs {
     RefineParams P;
     HashView h;
-    VisSegments seg;
+    VisList list;
     const void *sdf;
     const void *w;
     float inv_max_w;
@@ -303,16 +325,17 @@ hipError_t launch_refine_gather(int fmt, const HashView &h, const void *sdf, con
                                 int64_t n, float inv_max_w, float *out, hipStream_t st);
 
 hipError_t launch_range_clear(int32_t *cnt, int n, hipStream_t st);
-hipError_t launch_range_bin(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
-                            hipStream_t st);
-hipError_t launch_range_image(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
-                              float2 *zr, hipStream_t st);
+hipError_t launch_range_bin(const FrameGeom &g, const VisList &list, const RangeBins &rb, hipStream_t st);
+hipError_t launch_range_image(const FrameGeom &g, const VisList &list, const RangeBins &rb, float2 *zr,
+                              hipStream_t st);
 
 // launchers (one translation unit each)
-hipError_t launch_alloc(const AllocArgs &a, hipStream_t st);
-hipError_t launch_integrate(int fmt, const IntegrateArgs &a, hipStream_t st);
+hipError_t launch_alloc(const FuseArgs &a, hipStream_t st);
+hipError_t launch_integrate(int fmt, const FuseArgs &a, int grid, hipStream_t st);
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st);
-hipError_t launch_init(Bucket *b, int64_t nb, Excess *x, int64_t nx, uint8_t *vis, int64_t nvis,
+hipError_t launch_export_gather(int fmt, const void *sdf, const void *w, const int32_t *blocks, int64_t n,
+                                void *out_sdf, void *out_w, hipStream_t st);
+hipError_t launch_init(Bucket *b, int32_t *head, int64_t nb, Excess *x, int64_t nx, uint32_t *stamp, int64_t nstamp,
                        unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
                        Counters *cnt, int fmt, void *sdf, void *w, int64_t n_vox, hipStream_t st);
 
@@ -356,31 +379,13 @@ __device__ __forceinline__ uint32_t bfilt_index(int bx, int by, int bz)
 __device__ __forceinline__ int32_t find_block_direct(const HashView &h, int x, int y, int z)
 {
     if (!in_key_range(x, y, z)) return -1;
-    const unsigned long long key = pack_key(x, y, z);
-    const Bucket *B = h.buckets + hash_index(x, y, z, h.mask);
-    const ulonglong2 keys = *reinterpret_cast<const ulonglong2 *>(B->key);
-    const int4 rest = *reinterpret_cast<const int4 *>(&B->ptr[0]);
-    if (keys.x == key) return rest.x;
-    if (keys.y == key) return rest.y;
-    int32_t x_i = rest.z;
-    while (x_i >= 0) {
-        const Excess E = h.excess[x_i];
-        if (E.key == key) return E.ptr;
-        x_i = E.next;
-    }
-    return -1;
+    return probe_bucket(h, hash_index(x, y, z, h.mask), pack_key(x, y, z));
 }
 
-// key and block pointer of hash entry e (entry ids as in the layout above)
-__device__ __forceinline__ void entry_at(const HashView &h, int32_t e, unsigned long long &key, int32_t &ptr)
+// key of hash entry e (entry ids as in the layout above); the block is e itself
+__device__ __forceinline__ unsigned long long entry_key(const HashView &h, int32_t e)
 {
-    if (e < 2 * h.n_buckets) {
-        key = h.buckets[e >> 1].key[e & 1];
-        ptr = h.buckets[e >> 1].ptr[e & 1];
-    } else {
-        key = h.excess[e - 2 * h.n_buckets].key;
-        ptr = h.excess[e - 2 * h.n_buckets].ptr;
-    }
+    return e < 2 * h.n_buckets ? h.buckets[e >> 1].key[e & 1] : h.excess[e - 2 * h.n_buckets].key;
 }
 
 // ---------------------------------------------------------------------------
@@ -470,6 +475,50 @@ __device__ __forceinline__ void rect_tiles(const RangeRect &r, int &tx0, int &ty
     n = ntx * (r.v1 / kTile - ty0 + 1);
 }
 
+// ---------------------------------------------------------------------------
+// visible-list access
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int vis_count(const VisList &v, int s)
+{
+    const int c = v.cnt[32 * s];
+    return s < 32 ? min(c, v.cap) : c;
+}
+
+// Per-wave view of the list: lane s < 33 holds the inclusive prefix of the
+// segment counts, every lane the total.
+struct VisPrefix {
+    int incl, total;
+};
+__device__ __forceinline__ VisPrefix vis_prefix(const VisList &v, int lane)
+{
+    int incl = lane < kListSegs ? vis_count(v, lane) : 0;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(incl, o, kWave);
+        if (lane >= o) incl += y;
+    }
+    return VisPrefix{incl, __shfl(incl, kWave - 1, kWave)};
+}
+
+// record of item g < total, g the same on every lane of the wave
+__device__ __forceinline__ const VisRec &vis_item(const VisList &v, const VisPrefix &p, int g)
+{
+    const int s = __popcll(__ballot(p.incl <= g));   // segments wholly before g
+    const int excl = s ? __shfl(p.incl, s - 1, kWave) : 0;
+    return v.rec[(int64_t)s * v.cap + (g - excl)];
+}
+
+// record of item g < total, any g per thread: pre[s] = exclusive prefix of
+// segment s (pre[33] = total), e.g. staged in LDS
+__device__ __forceinline__ const VisRec &vis_item_at(const VisList &v, const int *pre, int g)
+{
+    int s = 0;
+#pragma unroll
+    for (int step = 32; step > 0; step >>= 1)
+        if (s + step < kListSegs && pre[s + step] <= g) s += step;
+    return v.rec[(int64_t)s * v.cap + (g - pre[s])];
+}
+
 // LDS of the per-tile range computation
 struct RangeLds {
     union {
@@ -478,15 +527,15 @@ struct RangeLds {
             uint32_t zlo[256], zhi[256];   // binary32 bits (all values >= 0: integer order = float order)
         } px;
     };
+    int pre[kListSegs + 1];
 };
 
 // Range of pixel (u, v) of tile (tx, ty) -- whole workgroup of 256 threads, one
 // pixel each (any mapping; (u, v) may lie outside the image).  Returns the empty
 // range (+inf, 0) where no rectangle covers the pixel.  A tile whose bin
 // overflowed recomputes every visible block's rectangle from the visible list.
-__device__ inline void tile_range(const FrameGeom &g, const HashView &h, const VisSegments &seg,
-                                  const RangeBins &rb, int tx, int ty, int u, int v, RangeLds &L, float &zlo,
-                                  float &zhi)
+__device__ inline void tile_range(const FrameGeom &g, const VisList &list, const RangeBins &rb, int tx, int ty,
+                                  int u, int v, RangeLds &L, float &zlo, float &zhi)
 {
     const int tile = ty * rb.tw + tx;
     const int n = rb.cnt[tile];
@@ -509,20 +558,22 @@ __device__ inline void tile_range(const FrameGeom &g, const HashView &h, const V
         return;
     }
     // overflow: every visible block, rectangles clipped to the tile, min / max
-    // by LDS atomics (threads stride over the list's segments)
+    // by LDS atomics (threads stride over the list)
     __syncthreads();
     L.px.zlo[threadIdx.x] = __float_as_uint(INFINITY);
     L.px.zhi[threadIdx.x] = 0u;
+    if (threadIdx.x < kWave) {
+        const VisPrefix p = vis_prefix(list, threadIdx.x);
+        if (threadIdx.x < kListSegs) L.pre[threadIdx.x + 1] = p.incl;
+        if (threadIdx.x == 0) L.pre[0] = 0;
+    }
     __syncthreads();
     const int ux0 = tx * kTile, vy0 = ty * kTile;
-    for (int sg = threadIdx.x; sg < seg.n_seg; sg += blockDim.x) {
-        const int c = seg.cnt[sg];
-        for (int i = 0; i < c; i++) {
-            unsigned long long key;
-            int32_t ptr;
-            entry_at(h, seg.list[(int64_t)sg * kSegEntries + i], key, ptr);
+    const int total = L.pre[kListSegs];
+    for (int i = threadIdx.x; i < total; i += blockDim.x) {
+        {
             int kx, ky, kz;
-            unpack_key(key, kx, ky, kz);
+            unpack_key(vis_item_at(list, L.pre, i).key, kx, ky, kz);
             RangeRect r;
             if (!block_rect(g, kx, ky, kz, r)) continue;
             const int a0 = max((int)r.u0, ux0), a1 = min((int)r.u1, ux0 + kTile - 1);

@@ -9,7 +9,7 @@
 // and tile, no per-pixel atomics), and the raycast's workgroup for a tile --
 // which covers exactly those 16 x 16 pixels -- takes the min / max over its bin
 // in registers, so the range image itself never goes through memory.  The
-// integration kernel bins at the frame's own pose as it integrates each block;
+// allocation kernel bins at the frame's own pose as it lists each visible block;
 // k_range_bin does it for a raycast at any other pose, from the visible list.
 #include <algorithm>
 
@@ -22,17 +22,20 @@ __global__ __launch_bounds__(256) void k_range_clear(int32_t *cnt, int n)
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cnt[i] = 0;
 }
 
-// workgroup b bins the blocks of visible-list segment b, one thread per block
-__global__ __launch_bounds__(256) void k_range_bin(FrameGeom g, HashView h, VisSegments seg, RangeBins rb)
+// one thread per visible block (grid-strided over the visible list)
+__global__ __launch_bounds__(256) void k_range_bin(FrameGeom g, VisList list, RangeBins rb)
 {
-    const int sg = blockIdx.x;
-    const int c = seg.cnt[sg];
-    for (int i = threadIdx.x; i < c; i += blockDim.x) {
-        unsigned long long key;
-        int32_t ptr;
-        entry_at(h, seg.list[(int64_t)sg * kSegEntries + i], key, ptr);
+    __shared__ int s_pre[kListSegs + 1];
+    if (threadIdx.x < kWave) {
+        const VisPrefix p = vis_prefix(list, threadIdx.x);
+        if (threadIdx.x < kListSegs) s_pre[threadIdx.x + 1] = p.incl;
+        if (threadIdx.x == 0) s_pre[0] = 0;
+    }
+    __syncthreads();
+    const int total = s_pre[kListSegs];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
         int kx, ky, kz;
-        unpack_key(key, kx, ky, kz);
+        unpack_key(vis_item_at(list, s_pre, i).key, kx, ky, kz);
         RangeRect r;
         if (!block_rect(g, kx, ky, kz, r)) continue;
         int tx0, ty0, ntx, n;
@@ -46,14 +49,13 @@ __global__ __launch_bounds__(256) void k_range_bin(FrameGeom g, HashView h, VisS
 }
 
 // the range image: one workgroup per tile, row-major pixels within it
-__global__ __launch_bounds__(256) void k_range_image(FrameGeom g, HashView h, VisSegments seg, RangeBins rb,
-                                                      float2 *zr)
+__global__ __launch_bounds__(256) void k_range_image(FrameGeom g, VisList list, RangeBins rb, float2 *zr)
 {
     __shared__ RangeLds L;
     const int tx = blockIdx.x % rb.tw, ty = blockIdx.x / rb.tw;
     const int u = tx * kTile + (threadIdx.x & (kTile - 1)), v = ty * kTile + threadIdx.x / kTile;
     float zlo, zhi;
-    tile_range(g, h, seg, rb, tx, ty, u, v, L, zlo, zhi);
+    tile_range(g, list, rb, tx, ty, u, v, L, zlo, zhi);
     if (u < g.W && v < g.H) zr[(int64_t)v * g.W + u] = make_float2(zlo, zhi);
 }
 
@@ -63,17 +65,16 @@ hipError_t launch_range_clear(int32_t *cnt, int n, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_range_bin(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
-                            hipStream_t st)
+hipError_t launch_range_bin(const FrameGeom &g, const VisList &list, const RangeBins &rb, hipStream_t st)
 {
-    k_range_bin<<<seg.n_seg, 256, 0, st>>>(g, h, seg, rb);
+    k_range_bin<<<256, 256, 0, st>>>(g, list, rb);
     return hipGetLastError();
 }
 
-hipError_t launch_range_image(const FrameGeom &g, const HashView &h, const VisSegments &seg, const RangeBins &rb,
-                              float2 *zr, hipStream_t st)
+hipError_t launch_range_image(const FrameGeom &g, const VisList &list, const RangeBins &rb, float2 *zr,
+                              hipStream_t st)
 {
-    k_range_image<<<rb.tw * rb.th, 256, 0, st>>>(g, h, seg, rb, zr);
+    k_range_image<<<rb.tw * rb.th, 256, 0, st>>>(g, list, rb, zr);
     return hipGetLastError();
 }
 

@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     float zlo = 0.0f, zhi = 0.0f;
     if (a.rb.cnt) {
         __shared__ RangeLds s_range;
-        tile_range(g, a.h, a.seg, a.rb, tx, ty, u, v, s_range, zlo, zhi);
+        tile_range(g, a.list, a.rb, tx, ty, u, v, s_range, zlo, zhi);
     }
     if (u >= g.W || v >= g.H) return;
     const int64_t pix = (int64_t)v * g.W + u;

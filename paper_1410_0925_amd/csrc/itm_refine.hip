@@ -350,13 +350,12 @@ __global__ __launch_bounds__(256) void k_refine_gated(RefineGateArgs a)
     const auto *Wv = (const typename V::Wt *)a.w;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, n = lane & 15;
-    // the visible list, segment by segment (workgroup-uniform loops)
-    for (int sg = blockIdx.x; sg < a.seg.n_seg; sg += gridDim.x)
-    for (int si = 0, sn = a.seg.cnt[sg]; si < sn; si++) {
-        const int32_t e = a.seg.list[(int64_t)sg * kSegEntries + si];
-        unsigned long long key;
-        int32_t ptr;
-        entry_at(a.h, e, key, ptr);
+    // the visible list (workgroup-uniform loop)
+    const VisPrefix vp = vis_prefix(a.list, lane);
+    for (int bi = blockIdx.x; bi < vp.total; bi += gridDim.x) {
+        const VisRec rec = vis_item(a.list, vp, bi);
+        const unsigned long long key = rec.key;
+        const int32_t ptr = rec.e;
         int kx, ky, kz;
         unpack_key(key, kx, ky, kz);
         // gate on the block's largest weight

@@ -69,12 +69,11 @@ struct itm_scene {
     int device, num_cu;
 
     Bucket *buckets = nullptr;
+    int32_t *head = nullptr;
     Excess *excess = nullptr;
-    uint8_t *vis = nullptr;
-    int64_t vis_bytes = 0;
-    int32_t *vis_list = nullptr;      // [n_seg][kSegEntries]
-    int32_t *seg_cnt = nullptr;       // [n_seg]
-    int32_t n_seg = 0;
+    uint32_t *vis_stamp = nullptr;    // [n_entries] frame (+1) of the last listing
+    VisRec *vis_rec = nullptr;        // [32 list_cap + n_entries] visible list records
+    int32_t list_cap = 0;             // records per list stripe
     void *sdf = nullptr;
     void *w = nullptr;
     unsigned long long *set = nullptr;
@@ -119,10 +118,10 @@ void release(itm_scene *sc)
     (void)hipStreamSynchronize(sc->stream);
     for (hipEvent_t e : sc->ev) (void)hipEventDestroy(e);
     (void)hipFree(sc->buckets);
+    (void)hipFree(sc->head);
     (void)hipFree(sc->excess);
-    (void)hipFree(sc->vis);
-    (void)hipFree(sc->vis_list);
-    (void)hipFree(sc->seg_cnt);
+    (void)hipFree(sc->vis_stamp);
+    (void)hipFree(sc->vis_rec);
     (void)hipFree(sc->bin_cnt);
     (void)hipFree(sc->bin_rect);
     (void)hipFree(sc->sdf);
@@ -191,14 +190,18 @@ itm_status make_geom(const itm_scene *sc, const itm_intrinsics *K, const double 
     return ITM_OK;
 }
 
-VisSegments segments(const itm_scene *sc)
+// the visible list of the frame with this parity (its counters live on the device)
+VisList vis_list(const itm_scene *sc, int parity)
 {
-    VisSegments v;
-    v.list = sc->vis_list;
-    v.cnt = sc->seg_cnt;
-    v.n_seg = sc->n_seg;
+    VisList v;
+    v.rec = sc->vis_rec;
+    v.cnt = &sc->cnt->lst[parity][0][0];
+    v.cap = sc->list_cap;
     return v;
 }
+
+// parity of the last integrated frame (1 before any: its counters are zero)
+int last_parity(const itm_scene *sc) { return (sc->frame - 1) & 1; }
 
 // bins for images of W x H pixels (grown on demand; growing clears them)
 itm_status ensure_bins(itm_scene *sc, int W, int H)
@@ -234,30 +237,11 @@ RangeBins bin_set(const itm_scene *sc, int set, int W, int H)
 
 HashView hash_view(const itm_scene *sc);
 
-// the bins holding the last frame's visible blocks at pose (K, T): the frame's
-// own bins when it was integrated at exactly this pose and image size, else
-// set 2, filled now
-itm_status bins_for_pose(itm_scene *sc, const itm_intrinsics *K, const double *T, const FrameGeom &g,
-                         RangeBins *rb)
-{
-    if (itm_status st = ensure_bins(sc, g.W, g.H)) return st;
-    const bool same = sc->fused_frame >= 0 && sc->fused_frame == sc->frame - 1 &&
-                      std::memcmp(&sc->fused_K, K, sizeof *K) == 0 &&
-                      std::memcmp(sc->fused_T, T, sizeof sc->fused_T) == 0;
-    if (same) {
-        *rb = bin_set(sc, sc->fused_frame & 1, g.W, g.H);
-        return ITM_OK;
-    }
-    *rb = bin_set(sc, 2, g.W, g.H);
-    HIP_TRY(launch_range_clear(rb->cnt, rb->tw * rb->th, sc->stream));
-    HIP_TRY(launch_range_bin(g, hash_view(sc), segments(sc), *rb, sc->stream));
-    return ITM_OK;
-}
-
 HashView hash_view(const itm_scene *sc)
 {
     HashView h;
     h.buckets = sc->buckets;
+    h.head = sc->head;
     h.excess = sc->excess;
     h.occ = sc->occ;
     h.macro = sc->occ + sc->occ_words;
@@ -299,6 +283,27 @@ struct ProfScope {
         if (slot >= 0) (void)hipEventRecord(sc->ev[2 * slot + 1], sc->stream);
     }
 };
+
+// the bins holding the last frame's visible blocks at pose (K, T): the frame's
+// own bins when it was integrated at exactly this pose and image size, else
+// set 2, filled now
+itm_status bins_for_pose(itm_scene *sc, const itm_intrinsics *K, const double *T, const FrameGeom &g,
+                         RangeBins *rb)
+{
+    if (itm_status st = ensure_bins(sc, g.W, g.H)) return st;
+    const bool same = sc->fused_frame >= 0 && sc->fused_frame == sc->frame - 1 &&
+                      std::memcmp(&sc->fused_K, K, sizeof *K) == 0 &&
+                      std::memcmp(sc->fused_T, T, sizeof sc->fused_T) == 0;
+    if (same) {
+        *rb = bin_set(sc, sc->fused_frame & 1, g.W, g.H);
+        return ITM_OK;
+    }
+    *rb = bin_set(sc, 2, g.W, g.H);
+    HIP_TRY(launch_range_clear(rb->cnt, rb->tw * rb->th, sc->stream));
+    HIP_TRY(launch_range_bin(g, vis_list(sc, last_parity(sc)), *rb, sc->stream));
+    return ITM_OK;
+}
+
 
 }  // namespace
 
@@ -368,18 +373,19 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
     }
     sc->num_cu = prop.multiProcessorCount;
     const int64_t n_vox = sc->vba_cap * kBlockVox;
-    sc->vis_bytes = (sc->n_entries + 15) / 16 * 16;
-    // one visible-list segment per integration workgroup (2048 flag bytes)
-    sc->n_seg = (int32_t)((sc->vis_bytes + kSegEntries - 1) / kSegEntries);
+    // visible list: 32 stripes sized for an even share plus slack, and an
+    // overflow segment that can hold every entry
+    sc->list_cap = (int32_t)((sc->n_entries + 31) / 32 + 4096);
     if (dev_alloc((void **)&sc->buckets, sizeof(Bucket) * n_buckets, "buckets") ||
+        dev_alloc((void **)&sc->head, sizeof(int32_t) * n_buckets, "bucket chain heads") ||
         dev_alloc((void **)&sc->excess, sizeof(Excess) * std::max<int64_t>(n_excess, 1), "excess") ||
-        dev_alloc((void **)&sc->vis, sc->vis_bytes, "vis") ||
-        dev_alloc((void **)&sc->vis_list, sizeof(int32_t) * kSegEntries * sc->n_seg, "vis_list") ||
-        dev_alloc((void **)&sc->seg_cnt, sizeof(int32_t) * sc->n_seg, "visible segment counts") ||
+        dev_alloc((void **)&sc->vis_stamp, sizeof(uint32_t) * sc->n_entries, "visibility stamps") ||
+        dev_alloc((void **)&sc->vis_rec, sizeof(VisRec) * (32 * (size_t)sc->list_cap + sc->n_entries),
+                  "visible list") ||
         dev_alloc(&sc->sdf, sdf_elem(fmt) * n_vox, "sdf") ||
         dev_alloc(&sc->w, w_elem(fmt) * n_vox, "weights") ||
-        dev_alloc((void **)&sc->set, sizeof(unsigned long long) * sc->set_size, "claim set") ||
-        dev_alloc((void **)&sc->set_list, sizeof(int32_t) * sc->set_size, "claim list") ||
+        dev_alloc((void **)&sc->set, sizeof(unsigned long long) * 2 * sc->set_size, "claim sets") ||
+        dev_alloc((void **)&sc->set_list, sizeof(int32_t) * 3 * sc->set_size, "claim lists") ||
         dev_alloc((void **)&sc->cnt, sizeof(Counters), "counters") ||
         dev_alloc((void **)&sc->occ,
                   sizeof(uint32_t) * ((n_buckets + 31) / 32 + kMacroWords + kBlockFilterWords),
@@ -388,10 +394,9 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
         return nullptr;
     }
     sc->occ_words = (n_buckets + 31) / 32;
-    hipError_t e = launch_init(sc->buckets, n_buckets, sc->excess, n_excess, sc->vis, sc->vis_bytes,
-                               sc->set, sc->set_size, sc->occ, sc->occ_words + kMacroWords + kBlockFilterWords,
+    hipError_t e = launch_init(sc->buckets, sc->head, n_buckets, sc->excess, n_excess, sc->vis_stamp, sc->n_entries,
+                               sc->set, 2 * sc->set_size, sc->occ, sc->occ_words + kMacroWords + kBlockFilterWords,
                                sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
-    if (e == hipSuccess) e = launch_range_clear(sc->seg_cnt, sc->n_seg, sc->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     if (e != hipSuccess) {
         fail(ITM_ERR_HIP, "scene initialisation failed: %s", hipGetErrorString(e));
@@ -426,44 +431,48 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
     const int32_t parity = sc->frame & 1;
     if (sc->range_on)
         if (itm_status st = ensure_bins(sc, g.W, g.H)) return st;
+    FuseArgs a;
     {
-        ProfScope ps(sc, 0);
-        AllocArgs a;
         a.fg = g;
         a.depth = depth;
         a.h = h;
-        a.vis = sc->vis;
-        a.set = sc->set;
-        a.set_list = sc->set_list;
-        a.set_mask = (uint32_t)(sc->set_size - 1);
         a.parity = parity;
+        a.stamp = sc->vis_stamp;
+        a.stamp_now = (uint32_t)sc->frame + 1u;
+        // claim sets: tables alternate by frame, slot lists and counts by frame % 3
+        const int f3 = sc->frame % 3, p3 = (sc->frame + 2) % 3, n3 = (sc->frame + 1) % 3;
+        a.set = sc->set + (size_t)parity * sc->set_size;
+        a.set_list = sc->set_list + (size_t)f3 * sc->set_size;
+        a.set_used = &sc->cnt->set_used[f3];
+        a.set_mask = (uint32_t)(sc->set_size - 1);
+        a.set_prev = sc->set + (size_t)(parity ^ 1) * sc->set_size;
+        a.set_list_prev = sc->set_list + (size_t)p3 * sc->set_size;
+        a.set_used_prev = &sc->cnt->set_used[p3];
+        a.set_used_next = &sc->cnt->set_used[n3];
+        a.list = vis_list(sc, parity);
+        a.list_clear = vis_list(sc, parity ^ 1).cnt;
+        a.rb = RangeBins{};
+        a.rb_clear = nullptr;
+        a.n_clear = 0;
+        if (sc->range_on) {   // bin the expected-depth rectangles at this pose
+            a.rb = bin_set(sc, parity, g.W, g.H);
+            a.rb_clear = bin_set(sc, parity ^ 1, g.W, g.H).cnt;
+            a.n_clear = (int32_t)sc->bin_tiles;
+        }
+        a.sdf = sc->sdf;
+        a.w = sc->w;
         a.cnt = sc->cnt;
+    }
+    {
+        ProfScope ps(sc, 0);
         HIP_TRY(launch_alloc(a, sc->stream));
     }
     {
         ProfScope ps(sc, 1);
-        IntegrateArgs ia;
-        ia.fg = g;
-        ia.depth = depth;
-        ia.h = h;
-        ia.vis8 = reinterpret_cast<uint2 *>(sc->vis);
-        ia.n_words8 = sc->vis_bytes / 8;
-        ia.set = sc->set;
-        ia.set_list = sc->set_list;
-        ia.parity = parity;
-        ia.seg = segments(sc);
-        ia.rb = RangeBins{};
-        ia.rb_clear = nullptr;
-        ia.n_clear = 0;
-        if (sc->range_on) {   // bin the expected-depth rectangles at this pose
-            ia.rb = bin_set(sc, parity, g.W, g.H);
-            ia.rb_clear = bin_set(sc, parity ^ 1, g.W, g.H).cnt;
-            ia.n_clear = (int32_t)sc->bin_tiles;
-        }
-        ia.sdf = sc->sdf;
-        ia.w = sc->w;
-        ia.cnt = sc->cnt;
-        HIP_TRY(launch_integrate(sc->fmt, ia, sc->stream));
+        // enough waves for about one block each at VGA (5 workgroups per CU),
+        // more for tables that can list more blocks; a multiple of 8 workgroups
+        const int grid = (int)std::min<int64_t>(std::max<int64_t>(sc->num_cu * 5, sc->n_entries / 2048), 16384) / 8 * 8;
+        HIP_TRY(launch_integrate(sc->fmt, a, grid, sc->stream));
     }
     sc->fused_frame = sc->range_on ? sc->frame : -1;
     if (sc->range_on) {
@@ -477,7 +486,7 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
         ra.P.Wt = sc->refiner->Wt;
         ra.P.bias = sc->refiner->bias;
         ra.h = h;
-        ra.seg = segments(sc);
+        ra.list = vis_list(sc, parity);
         ra.sdf = sc->sdf;
         ra.w = sc->w;
         ra.inv_max_w = 1.0f / (float)sc->max_w;
@@ -507,7 +516,7 @@ itm_status itm_raycast(itm_scene *sc, const itm_intrinsics *K, const double *T_w
     a.pts = reinterpret_cast<float4 *>(out_pts);
     a.nrm = reinterpret_cast<float4 *>(out_normals);
     a.rb = RangeBins{};
-    a.seg = segments(sc);
+    a.list = vis_list(sc, last_parity(sc));
     if (sc->range_on)
         if (itm_status st = bins_for_pose(sc, K, T_wc, g, &a.rb)) return st;
     HIP_TRY(launch_raycast(sc->fmt, a, sc->stream));
@@ -543,7 +552,7 @@ itm_status itm_expected_depths(itm_scene *sc, const itm_intrinsics *K, const dou
     if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
     RangeBins rb;
     if (itm_status st = bins_for_pose(sc, K, T_wc, g, &rb)) return st;
-    HIP_TRY(launch_range_image(g, hash_view(sc), segments(sc), rb, reinterpret_cast<float2 *>(zrange),
+    HIP_TRY(launch_range_image(g, vis_list(sc, last_parity(sc)), rb, reinterpret_cast<float2 *>(zrange),
                                sc->stream));
     return ITM_OK;
 }
@@ -557,8 +566,8 @@ itm_status itm_get_stats(itm_scene *sc, itm_stats *out)
     out->n_allocated = std::min<int64_t>(c.vba_next, sc->vba_cap);
     unsigned long long v_last = 0, v_tot = 0;
     for (int i = 0; i < kStripes; i++) {
-        v_last += c.vis[0][i][0];
-        v_tot += c.vis[1][i][0];
+        v_last += c.vis[last_parity(sc)][i][0];
+        v_tot += c.vis[2][i][0];
     }
     out->n_visible_last = (int64_t)v_last;
     out->n_excess_used = std::min<int64_t>(c.excess_next, sc->n_excess);
@@ -566,8 +575,8 @@ itm_status itm_get_stats(itm_scene *sc, itm_stats *out)
     out->vba_capacity = sc->vba_cap;
     unsigned long long u_last = 0, u_tot = 0;
     for (int i = 0; i < kStripes; i++) {
-        u_last += c.upd[0][i][0];
-        u_tot += c.upd[1][i][0];
+        u_last += c.upd[last_parity(sc)][i][0];
+        u_tot += c.upd[2][i][0];
     }
     out->n_updated_last = (int64_t)u_last;
     out->n_entries = sc->n_entries;
@@ -577,10 +586,15 @@ itm_status itm_get_stats(itm_scene *sc, itm_stats *out)
     return ITM_OK;
 }
 
-itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *w, int64_t capacity,
-                             int64_t *n_blocks)
+}  // extern "C"
+
+namespace {
+
+struct BlockRec { int32_t x, y, z, blk; };
+
+// every allocated block (key and voxel block = entry id), sorted by (x, y, z)
+itm_status collect_blocks(itm_scene *sc, std::vector<BlockRec> &recs)
 {
-    if (!sc || !n_blocks) return fail(ITM_ERR_ARG, "NULL scene or n_blocks");
     std::vector<Bucket> hb(sc->n_buckets);
     std::vector<Excess> hx(std::max<int64_t>(sc->n_excess, 1));
     HIP_TRY(hipMemcpyAsync(hb.data(), sc->buckets, sizeof(Bucket) * sc->n_buckets, hipMemcpyDeviceToHost,
@@ -589,42 +603,74 @@ itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *
         HIP_TRY(hipMemcpyAsync(hx.data(), sc->excess, sizeof(Excess) * sc->n_excess, hipMemcpyDeviceToHost,
                                sc->stream));
     HIP_TRY(hipStreamSynchronize(sc->stream));
-    struct Rec { int32_t x, y, z, ptr; };
-    std::vector<Rec> recs;
-    auto add = [&](unsigned long long k, int32_t p) {
-        if (!(k & kKeyValid) || p < 0) return;
-        Rec r;
+    recs.clear();
+    auto add = [&](unsigned long long k, int64_t e) {
+        if (!(k & kKeyValid)) return;
+        BlockRec r;
         r.x = (int16_t)(k & 0xffff);
         r.y = (int16_t)((k >> 16) & 0xffff);
         r.z = (int16_t)((k >> 32) & 0xffff);
-        r.ptr = p;
+        r.blk = (int32_t)e;
         recs.push_back(r);
     };
-    for (const Bucket &b : hb) { add(b.key[0], b.ptr[0]); add(b.key[1], b.ptr[1]); }
-    for (int64_t i = 0; i < sc->n_excess; i++) add(hx[i].key, hx[i].ptr);
-    std::sort(recs.begin(), recs.end(), [](const Rec &a, const Rec &b) {
+    for (int64_t b = 0; b < sc->n_buckets; b++) {
+        add(hb[b].key[0], 2 * b);
+        add(hb[b].key[1], 2 * b + 1);
+    }
+    for (int64_t i = 0; i < sc->n_excess; i++) add(hx[i].key, 2 * sc->n_buckets + i);
+    std::sort(recs.begin(), recs.end(), [](const BlockRec &a, const BlockRec &b) {
         if (a.x != b.x) return a.x < b.x;
         if (a.y != b.y) return a.y < b.y;
         return a.z < b.z;
     });
-    *n_blocks = (int64_t)recs.size();
+    return ITM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *w, int64_t capacity,
+                             int64_t *n_blocks)
+{
+    if (!sc || !n_blocks) return fail(ITM_ERR_ARG, "NULL scene or n_blocks");
+    std::vector<BlockRec> recs;
+    if (itm_status st = collect_blocks(sc, recs)) return st;
+    const int64_t n = (int64_t)recs.size();
+    *n_blocks = n;
     if (!coords && !sdf && !w) return ITM_OK;
-    if (capacity < (int64_t)recs.size())
-        return fail(ITM_ERR_ARG, "capacity %lld < %zu blocks", (long long)capacity, recs.size());
-    const int32_t n_used = recs.empty() ? 0 : std::max_element(recs.begin(), recs.end(), [](const Rec &a, const Rec &b) {
-                                                   return a.ptr < b.ptr;
-                                               })->ptr + 1;
-    std::vector<uint8_t> hs, hw;
-    if (sdf) hs.resize(sdf_elem(sc->fmt) * kBlockVox * (size_t)n_used);
-    if (w) hw.resize(w_elem(sc->fmt) * kBlockVox * (size_t)n_used);
-    if (sdf && n_used)
-        HIP_TRY(hipMemcpyAsync(hs.data(), sc->sdf, hs.size(), hipMemcpyDeviceToHost, sc->stream));
-    if (w && n_used) HIP_TRY(hipMemcpyAsync(hw.data(), sc->w, hw.size(), hipMemcpyDeviceToHost, sc->stream));
-    HIP_TRY(hipStreamSynchronize(sc->stream));
-    for (size_t i = 0; i < recs.size(); i++) {
-        const Rec &r = recs[i];
-        if (coords) { coords[3 * i] = r.x; coords[3 * i + 1] = r.y; coords[3 * i + 2] = r.z; }
-        const size_t src = (size_t)r.ptr * kBlockVox;
+    if (capacity < n) return fail(ITM_ERR_ARG, "capacity %lld < %lld blocks", (long long)capacity, (long long)n);
+    for (int64_t i = 0; i < n && coords; i++) {
+        coords[3 * i] = recs[i].x;
+        coords[3 * i + 1] = recs[i].y;
+        coords[3 * i + 2] = recs[i].z;
+    }
+    if ((!sdf && !w) || n == 0) return ITM_OK;
+    // the blocks' voxels, packed on the device in export order, then one copy
+    const size_t es = sdf_elem(sc->fmt), ew = w_elem(sc->fmt);
+    std::vector<int32_t> blk(n);
+    for (int64_t i = 0; i < n; i++) blk[i] = recs[i].blk;
+    int32_t *d_blk = nullptr;
+    void *d_s = nullptr, *d_w = nullptr;
+    itm_status st = dev_alloc((void **)&d_blk, sizeof(int32_t) * n, "export list");
+    if (!st && sdf) st = dev_alloc(&d_s, es * kBlockVox * n, "export sdf");
+    if (!st && w) st = dev_alloc(&d_w, ew * kBlockVox * n, "export weights");
+    std::vector<uint8_t> hs(sdf ? es * kBlockVox * n : 0), hw(w ? ew * kBlockVox * n : 0);
+    hipError_t e = hipSuccess;
+    if (!st) {
+        e = hipMemcpyAsync(d_blk, blk.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, sc->stream);
+        if (e == hipSuccess) e = launch_export_gather(sc->fmt, sc->sdf, sc->w, d_blk, n, d_s, d_w, sc->stream);
+        if (e == hipSuccess && sdf) e = hipMemcpyAsync(hs.data(), d_s, hs.size(), hipMemcpyDeviceToHost, sc->stream);
+        if (e == hipSuccess && w) e = hipMemcpyAsync(hw.data(), d_w, hw.size(), hipMemcpyDeviceToHost, sc->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    }
+    (void)hipFree(d_blk);
+    (void)hipFree(d_s);
+    (void)hipFree(d_w);
+    if (st) return st;
+    if (e != hipSuccess) return fail(ITM_ERR_HIP, "export failed: %s", hipGetErrorString(e));
+    for (int64_t i = 0; i < n; i++) {
+        const size_t src = (size_t)i * kBlockVox;
         for (int l = 0; l < kBlockVox; l++) {
             if (sdf) {
                 float f;
@@ -638,7 +684,7 @@ itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *
                     std::memcpy(&q, &hs[2 * (src + l)], 2);
                     f = (float)q / 32767.0f;
                 }
-                sdf[i * kBlockVox + l] = f;
+                sdf[src + l] = f;
             }
             if (w) {
                 float wf;
@@ -648,7 +694,7 @@ itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *
                     std::memcpy(&hv, &hw[2 * (src + l)], 2);
                     wf = __half2float(hv);
                 } else wf = (float)hw[src + l];
-                w[i * kBlockVox + l] = wf;
+                w[src + l] = wf;
             }
         }
     }
@@ -857,32 +903,16 @@ itm_status itm_export_blocks_refined(itm_scene *sc, int32_t *coords, float *sdf,
         if (refined && coords) std::memset(refined, 0, (size_t)*n_blocks);
         return ITM_OK;
     }
-    // block pointers of the exported (sorted) blocks
-    std::vector<Bucket> hb(sc->n_buckets);
-    std::vector<Excess> hx(std::max<int64_t>(sc->n_excess, 1));
-    HIP_TRY(hipMemcpyAsync(hb.data(), sc->buckets, sizeof(Bucket) * sc->n_buckets, hipMemcpyDeviceToHost,
-                           sc->stream));
-    if (sc->n_excess)
-        HIP_TRY(hipMemcpyAsync(hx.data(), sc->excess, sizeof(Excess) * sc->n_excess, hipMemcpyDeviceToHost,
-                               sc->stream));
+    // voxel blocks of the exported (sorted) blocks
+    std::vector<BlockRec> recs;
+    if (itm_status st = collect_blocks(sc, recs)) return st;
     std::vector<int32_t> stamps(sc->vba_cap);
     HIP_TRY(hipMemcpyAsync(stamps.data(), sc->stamp, sizeof(int32_t) * sc->vba_cap, hipMemcpyDeviceToHost,
                            sc->stream));
     HIP_TRY(hipStreamSynchronize(sc->stream));
-    auto ptr_of = [&](int32_t x, int32_t y, int32_t z) -> int32_t {
-        const unsigned long long key = kKeyValid | (unsigned long long)(uint16_t)x |
-                                       ((unsigned long long)(uint16_t)y << 16) |
-                                       ((unsigned long long)(uint16_t)z << 32);
-        const uint32_t b = (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u)) & sc->mask;
-        if (hb[b].key[0] == key) return hb[b].ptr[0];
-        if (hb[b].key[1] == key) return hb[b].ptr[1];
-        for (int32_t i = hb[b].head; i >= 0; i = hx[i].next)
-            if (hx[i].key == key) return hx[i].ptr;
-        return -1;
-    };
     std::vector<__half> blk(kBlockVox);
     for (int64_t i = 0; i < *n_blocks; i++) {
-        const int32_t p = ptr_of(coords[3 * i], coords[3 * i + 1], coords[3 * i + 2]);
+        const int32_t p = recs[i].blk;
         const bool r = p >= 0 && stamps[p] == sc->frame && sc->frame > 0;
         if (refined) refined[i] = r ? 1 : 0;
         if (!r) continue;
