@@ -29,15 +29,22 @@ SDF_BYTES = {"f32": 4, "f16": 2, "s16u8": 2}
 VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 
 
-# Hardware byte counters of the kernels on this workload, per dispatch, from
-#   rocprofv3 --pmc FETCH_SIZE (resp. WRITE_SIZE) -- python3 bench.py --steps 20
-#   --warmup 10 --no-cpu-baseline --no-learned --no-events --calib-copy-mb 256
-# (summaries under profiles/).  The same counters read for the 256 MiB reference
-# copy give the scale factors: FETCH_SIZE reports half of the bytes read, WRITE_SIZE
-# all of the bytes written.  `src` is the SHA-256 of the kernel's source files when
-# the counters were taken; a changed kernel reports traffic null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.75, 262144.0 / 262144.0
-TRAFFIC_KIB = {}
+# Hardware byte counters of the kernels on this workload, KiB per dispatch,
+# averaged over the bench's timed frames 10..299 (search range on), from
+#   rocprofv3 --pmc FETCH_SIZE (resp. WRITE_SIZE) -- python3 bench.py
+#   --no-cpu-baseline --no-learned --no-events --calib-copy-mb 256
+# (summaries under profiles/).  FETCH_SIZE counts 64 B per read request while
+# these kernels' read requests are 128 B (TCC_EA0_RDREQ_128B): the reference
+# elementwise kernel that reads 256 MiB reports 131,090 KiB, hence the factor 2;
+# WRITE_SIZE reports the 256 MiB it writes exactly.  `src` is a SHA-256 prefix of
+# the kernel's source files when the counters were taken; a changed kernel
+# reports traffic null.
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.8, 262144.0 / 262144.0
+TRAFFIC_KIB = {
+    ("alloc", "f32", "vga"): {"fetch": 1021.8, "write": 1204.7, "src": "0730dadb3031ee60"},
+    ("integrate", "f32", "vga"): {"fetch": 10010.5, "write": 14770.6, "src": "0730dadb3031ee60"},
+    ("raycast", "f32", "vga"): {"fetch": 5224.6, "write": 9600.0, "src": "cb54ff4904f5b982"},
+}
 
 
 def kernel_source_sha(name):
@@ -137,17 +144,21 @@ def cpu_baseline(stream, seconds, search_range):
         if time.perf_counter() - t0 > seconds:
             break
     t_int = time.perf_counter() - t0
-    t1 = time.perf_counter()
+    # raycasts from the last frame's pose until about a third as much time again
+    t1, n_rc = time.perf_counter(), 0
     args = (stream.width, stream.height, stream.intrinsics, stream.T_wc[n - 1])
-    zr = sc.expected_depths(*args) if search_range else None
-    sc.raycast(*args, zrange=zr)
+    while n_rc < 1 or time.perf_counter() - t1 < t_int / 3:
+        zr = sc.expected_depths(*args) if search_range else None
+        sc.raycast(*args, zrange=zr)
+        n_rc += 1
     t_rc = time.perf_counter() - t1
     what = "expected depths + ranged raycast" if search_range else "raycast"
+    rays = n_rc * stream.width * stream.height / t_rc
     return {"value": vox / t_int, "unit": "voxels/s", "cores": oracle.num_threads(), "kind": "oracle",
             "sample": f"frames 0..{n - 1} of the same stream, allocation + integration "
-                      f"({t_int:.1f} s); {what} of frame {n - 1}: "
-                      f"{stream.width * stream.height / t_rc:.3g} rays/s",
-            "rays_per_s": stream.width * stream.height / t_rc}
+                      f"({t_int:.1f} s); {what} at frame {n - 1}'s pose, {n_rc} times "
+                      f"({t_rc:.1f} s): {rays:.3g} rays/s",
+            "rays_per_s": rays}
 
 
 def main():
@@ -227,7 +238,7 @@ def main():
         a = torch.ones(n, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)
+        torch.mul(a, 1.0, out=b)   # one elementwise kernel: reads a, writes b
         torch.cuda.synchronize()
         log(f"calibration copy: {args.calib_copy_mb} MiB read + {args.calib_copy_mb} MiB written")
 
@@ -255,7 +266,7 @@ def main():
         k = kernels[best]
         roofline = {"bound": "hbm", "kernel": best, "achieved": k["achieved_GBs"], "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": k["frac_hbm"], "traffic": k["traffic_bytes"]}
-    gpu_ms = sum(ms for ms, _ in prof.values()) if prof else None
+    gpu_ms = sum(ms / n for ms, n in prof.values() if n) if prof else None   # per frame
     out = {
         "metric": METRIC,
         "value": voxels / wall,
@@ -277,7 +288,7 @@ def main():
         "rays_per_s": rays / wall,
         "updated_voxels_per_s": upd_total / wall,
         "visible_blocks_per_frame": vis_total / args.steps,
-        "gpu_kernel_ms_per_step": None if gpu_ms is None else gpu_ms / args.steps,
+        "gpu_kernel_ms_per_step": gpu_ms,
         "kernels": kernels,
         "roofline": roofline,
     }
