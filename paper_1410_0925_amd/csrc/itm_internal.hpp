@@ -15,12 +15,14 @@
 //   bins     3 x n_tiles x (4 B + cap x 16 B)   expected-depth rectangles binned
 //                               by 16 x 16 pixel tile (two frame parities + one
 //                               for raycasts at another pose)
-//   sdf, w   n_entries x 512    voxel block array, structure of arrays, one
+//   sdf, w   (n_entries + 1) x 512  voxel block array, structure of arrays, one
 //                               element type per storage form.  The array has a
 //                               block for every hash entry, so the paper's
 //                               pointer into it is the entry id itself: a probe
 //                               that finds the key has the block, with no second
-//                               load and no free-list pop on insertion
+//                               load and no free-list pop on insertion.  The
+//                               block past the last entry is never written: its
+//                               voxels keep F = 1 (the value of an absent block)
 //   set      2 x R x u64        per-frame sets of blocks claimed for the excess list
 //                               (alternating by frame)
 //   cnt      Counters           device counters
@@ -196,8 +198,9 @@ struct FrameGeom {
     double Rwc[9], twc[3];
     double Rcw[9], tcw[3];
     float g[3][3];                      // g[j][a]: camera-frame step of one voxel along world axis j
+    float o_vox[3];                     // camera centre in voxel units, (float)(t_wc / s)
     // scene
-    double s, inv_bs;                   // voxel size, 1 / (8 s)
+    double s, inv_s, inv_bs;            // voxel size, 1 / s, 1 / (8 s)
     float s_f, mu_f, max_w_f;
     double mu;
     float z_near, z_far;
@@ -530,21 +533,39 @@ struct RangeLds {
     int pre[kListSegs + 1];
 };
 
-// Range of pixel (u, v) of tile (tx, ty) -- whole workgroup of 256 threads, one
-// pixel each (any mapping; (u, v) may lie outside the image).  Returns the empty
-// range (+inf, 0) where no rectangle covers the pixel.  A tile whose bin
-// overflowed recomputes every visible block's rectangle from the visible list.
-__device__ inline void tile_range(const FrameGeom &g, const VisList &list, const RangeBins &rb, int tx, int ty,
-                                  int u, int v, RangeLds &L, float &zlo, float &zhi)
+// A tile's bin count and, speculatively, its first 256 rectangles (those lie
+// inside the tile's storage whatever the count): issued together, one memory
+// round; a caller can issue them before other work it has to wait for.
+struct TileBin {
+    int n;
+    RangeRect first;
+};
+__device__ __forceinline__ TileBin tile_bin(const RangeBins &rb, int tx, int ty)
 {
     const int tile = ty * rb.tw + tx;
-    const int n = rb.cnt[tile];
+    TileBin b;
+    if ((int)threadIdx.x < rb.cap) b.first = rb.rect[(int64_t)tile * rb.cap + threadIdx.x];
+    b.n = rb.cnt[tile];
+    return b;
+}
+
+// Range of pixel (u, v) of tile (tx, ty) -- whole workgroup of 256 threads, one
+// pixel each (any mapping; (u, v) may lie outside the image), bin as loaded by
+// tile_bin.  Returns the empty range (+inf, 0) where no rectangle covers the
+// pixel.  A tile whose bin overflowed recomputes every visible block's
+// rectangle from the visible list.
+__device__ inline void tile_range(const FrameGeom &g, const VisList &list, const RangeBins &rb, int tx, int ty,
+                                  const TileBin &bin, int u, int v, RangeLds &L, float &zlo, float &zhi)
+{
+    const int tile = ty * rb.tw + tx;
+    const int n = bin.n;
     zlo = INFINITY;
     zhi = 0.0f;
     if (n <= rb.cap) {
         for (int base = 0; base < n; base += 256) {
             __syncthreads();
-            if (base + (int)threadIdx.x < n) L.rect[threadIdx.x] = rb.rect[(int64_t)tile * rb.cap + base + threadIdx.x];
+            if (base + (int)threadIdx.x < n)
+                L.rect[threadIdx.x] = base == 0 ? bin.first : rb.rect[(int64_t)tile * rb.cap + base + threadIdx.x];
             __syncthreads();
             const int m = min(256, n - base);
             for (int j = 0; j < m; j++) {

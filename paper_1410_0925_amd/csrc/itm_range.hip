@@ -55,7 +55,8 @@ __global__ __launch_bounds__(256) void k_range_image(FrameGeom g, VisList list, 
     const int tx = blockIdx.x % rb.tw, ty = blockIdx.x / rb.tw;
     const int u = tx * kTile + (threadIdx.x & (kTile - 1)), v = ty * kTile + threadIdx.x / kTile;
     float zlo, zhi;
-    tile_range(g, list, rb, tx, ty, u, v, L, zlo, zhi);
+    const TileBin bin = tile_bin(rb, tx, ty);
+    tile_range(g, list, rb, tx, ty, bin, u, v, L, zlo, zhi);
     if (u < g.W && v < g.H) zr[(int64_t)v * g.W + u] = make_float2(zlo, zhi);
 }
 

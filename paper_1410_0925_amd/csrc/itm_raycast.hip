@@ -89,23 +89,30 @@ struct Cube {
             p[c] = need && maybe ? find_block_direct(h, kx, ky, kz) : -1;
         }
     }
-    __device__ float F(const typename Vox<FMT>::S *sdf, int vx, int vy, int vz) const
-    {
-        const bool ex = (vx >> 3) != bx0, ey = (vy >> 3) != by0, ez = (vz >> 3) != bz0;
-        const int32_t a0 = ex ? p[1] : p[0], a1 = ex ? p[3] : p[2];
-        const int32_t a2 = ex ? p[5] : p[4], a3 = ex ? p[7] : p[6];
-        const int32_t b0 = ey ? a1 : a0, b1 = ey ? a3 : a2;
-        const int32_t ptr = ez ? b1 : b0;
-        if (ptr < 0) return 1.0f;
-        return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7)]);
-    }
-    // the 8 lattice voxels of the cell with corner i
-    __device__ void cell(const typename Vox<FMT>::S *sdf, int ix, int iy, int iz, float Fc[8]) const
-    {
-#pragma unroll
-        for (int c = 0; c < 8; c++) Fc[c] = F(sdf, ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1));
-    }
 };
+
+// Voxel reads of a Cube: a short select of the voxel's block, then one load (an
+// absent block reads as F = 1)
+template <int FMT>
+__device__ __forceinline__ float cube_F(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int vx, int vy, int vz)
+{
+    const bool ex = (vx >> 3) != cb.bx0, ey = (vy >> 3) != cb.by0, ez = (vz >> 3) != cb.bz0;
+    const int32_t a0 = ex ? cb.p[1] : cb.p[0], a1 = ex ? cb.p[3] : cb.p[2];
+    const int32_t a2 = ex ? cb.p[5] : cb.p[4], a3 = ex ? cb.p[7] : cb.p[6];
+    const int32_t b0 = ey ? a1 : a0, b1 = ey ? a3 : a2;
+    const int32_t ptr = ez ? b1 : b0;
+    if (ptr < 0) return 1.0f;
+    return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7)]);
+}
+
+// the 8 lattice voxels of the cell with corner i
+template <int FMT>
+__device__ __forceinline__ void cube_cell(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int ix, int iy,
+                                          int iz, float Fc[8])
+{
+#pragma unroll
+    for (int c = 0; c < 8; c++) Fc[c] = cube_F(cb, sdf, ix + (c & 1), iy + ((c >> 1) & 1), iz + ((c >> 2) & 1));
+}
 
 __device__ __forceinline__ float trilinear8(const float Fc[8], float rx, float ry, float rz)
 {
@@ -125,16 +132,16 @@ template <int FMT>
 __device__ __forceinline__ void stencil(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int ix, int iy,
                                         int iz, float Fc[8], float Ex[2][4], float Ey[2][4], float Ez[2][4])
 {
-    cb.cell(sdf, ix, iy, iz, Fc);
+    cube_cell(cb, sdf, ix, iy, iz, Fc);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int a0 = k & 1, a1 = k >> 1;
-        Ex[0][k] = cb.F(sdf, ix - 1, iy + a0, iz + a1);
-        Ex[1][k] = cb.F(sdf, ix + 2, iy + a0, iz + a1);
-        Ey[0][k] = cb.F(sdf, ix + a0, iy - 1, iz + a1);
-        Ey[1][k] = cb.F(sdf, ix + a0, iy + 2, iz + a1);
-        Ez[0][k] = cb.F(sdf, ix + a0, iy + a1, iz - 1);
-        Ez[1][k] = cb.F(sdf, ix + a0, iy + a1, iz + 2);
+        Ex[0][k] = cube_F(cb, sdf, ix - 1, iy + a0, iz + a1);
+        Ex[1][k] = cube_F(cb, sdf, ix + 2, iy + a0, iz + a1);
+        Ey[0][k] = cube_F(cb, sdf, ix + a0, iy - 1, iz + a1);
+        Ey[1][k] = cube_F(cb, sdf, ix + a0, iy + 2, iz + a1);
+        Ez[0][k] = cube_F(cb, sdf, ix + a0, iy + a1, iz - 1);
+        Ez[1][k] = cube_F(cb, sdf, ix + a0, iy + a1, iz + 2);
     }
 }
 
@@ -170,6 +177,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const FrameGeom &g = a.fg;
     int tx, ty;
     if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;  // whole workgroup
+    // the tile's expected-depth bin, loaded while the filters are staged
+    TileBin bin;
+    if (a.rb.cnt) bin = tile_bin(a.rb, tx, ty);
     // the macro-cell and block filters, staged in LDS: empty-space tests cost an
     // LDS read (they are contiguous in global memory)
     __shared__ uint32_t s_filt[kMacroWords + kBlockFilterWords];
@@ -188,19 +198,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     float zlo = 0.0f, zhi = 0.0f;
     if (a.rb.cnt) {
         __shared__ RangeLds s_range;
-        tile_range(g, a.list, a.rb, tx, ty, u, v, s_range, zlo, zhi);
+        tile_range(g, a.list, a.rb, tx, ty, bin, u, v, s_range, zlo, zhi);
     }
     if (u >= g.W || v >= g.H) return;
     const int64_t pix = (int64_t)v * g.W + u;
 
-    // binary64 ray set-up, rounded once
-    const double cdx = ((double)u - g.cxd) / g.fxd, cdy = ((double)v - g.cyd) / g.fyd;
+    // binary64 ray set-up, rounded once (the camera centre in voxel units comes
+    // from the host)
+    const double cdx = ((double)u - g.cxd) * g.inv_fx, cdy = ((double)v - g.cyd) * g.inv_fy;
     const double len = sqrt(cdx * cdx + cdy * cdy + 1.0);
-    double dir[3];
-#pragma unroll
-    for (int c = 0; c < 3; c++) dir[c] = (g.Rwc[3 * c] * cdx + g.Rwc[3 * c + 1] * cdy + g.Rwc[3 * c + 2]) / len;
-    const float ox = (float)(g.twc[0] / g.s), oy = (float)(g.twc[1] / g.s), oz = (float)(g.twc[2] / g.s);
-    const float dx = (float)(dir[0] / g.s), dy = (float)(dir[1] / g.s), dz = (float)(dir[2] / g.s);
+    const double w = g.inv_s / len;   // unit direction, in voxels per metre of t
+    const float ox = g.o_vox[0], oy = g.o_vox[1], oz = g.o_vox[2];
+    const float dx = (float)((g.Rwc[0] * cdx + g.Rwc[1] * cdy + g.Rwc[2]) * w);
+    const float dy = (float)((g.Rwc[3] * cdx + g.Rwc[4] * cdy + g.Rwc[5]) * w);
+    const float dz = (float)((g.Rwc[6] * cdx + g.Rwc[7] * cdy + g.Rwc[8]) * w);
     // search range: [z_near, z_far], narrowed to the expected range when there is one
     double t0 = (double)g.z_near * len, t1 = (double)g.z_far * len;
     if (a.rb.cnt) {
@@ -215,8 +226,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const float s = g.s_f, mu = g.mu_f, bs = 8.0f * g.s_f;
     const int fine_budget = (int)ceilf(bs / mu) + 1;
     const int cap = (int)((t_far - t_near) / s) * 4 + 1000;
-    // reciprocal direction for the macro-cell exit
-    const float idx = 1.0f / dx, idy = 1.0f / dy, idz = 1.0f / dz;
+    // Macro-cell exit, per axis: the exit plane's offset from the cell's low
+    // corner (the cell shrunk by 1e-3 voxel against rounding) and the reciprocal
+    // direction; an axis the ray does not move along never exits.
+    const float e_mc = 1e-3f;
+    const float ex = dx > 0.0f ? 32.0f - e_mc : e_mc, ey = dy > 0.0f ? 32.0f - e_mc : e_mc;
+    const float ez = dz > 0.0f ? 32.0f - e_mc : e_mc;
+    const float idx = dx != 0.0f ? 1.0f / dx : 0.0f, idy = dy != 0.0f ? 1.0f / dy : 0.0f;
+    const float idz = dz != 0.0f ? 1.0f / dz : 0.0f;
+    const float inv_bs = 1.0f / bs;
 
     const uint32_t *s_bfilt = s_filt + kMacroWords;
     BlockReader<FMT> rd(a.h, a.sdf, s_bfilt);
@@ -233,18 +251,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                 // miss: jump over them, keeping the sample spacing of 8 s.  The cell
                 // in sample space is [32 m - 1/2, 32 (m + 1) - 1/2) per axis, shrunk
                 // by 1e-3 voxel against rounding.
-                const float e = 1e-3f;
                 const float lx = (float)((bx >> kMacroShift) * 32) - 0.5f;
                 const float ly = (float)((by >> kMacroShift) * 32) - 0.5f;
                 const float lz = (float)((bz >> kMacroShift) * 32) - 0.5f;
-                const float tx = dx > 0.0f ? (lx + 32.0f - e - ox) * idx
-                                 : dx < 0.0f ? (lx + e - ox) * idx : INFINITY;
-                const float ty = dy > 0.0f ? (ly + 32.0f - e - oy) * idy
-                                 : dy < 0.0f ? (ly + e - oy) * idy : INFINITY;
-                const float tz = dz > 0.0f ? (lz + 32.0f - e - oz) * idz
-                                 : dz < 0.0f ? (lz + e - oz) * idz : INFINITY;
+                const float tx = dx != 0.0f ? (lx + ex - ox) * idx : INFINITY;
+                const float ty = dy != 0.0f ? (ly + ey - oy) * idy : INFINITY;
+                const float tz = dz != 0.0f ? (lz + ez - oz) * idz : INFINITY;
                 const float t_exit = fminf(tx, fminf(ty, tz));
-                const float m = fmaxf(ceilf((t_exit - t) / bs), 1.0f);
+                // samples to skip, rounded down by a relative 2^-20 so that the
+                // product's rounding never skips past the exit (one sample too
+                // few only costs another skip)
+                const float m = fmaxf(ceilf((t_exit - t) * inv_bs * (1.0f - 0x1p-20f)), 1.0f);
                 t = fmaf(m, bs, t);
                 continue;
             }
@@ -284,7 +301,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         Cube<FMT> cb;
         cb.fetch(a.h, s_bfilt, ix - 3, iy - 3, iz - 3, ix + 4, iy + 4, iz + 4);
         float Fc[8];
-        cb.cell(sdf, ix, iy, iz, Fc);
+        cube_cell(cb, sdf, ix, iy, iz, Fc);
         t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
         // Second refinement: its cell and, speculatively, the normal stencil
         // around it.  The final point nearly always stays in that cell; when it

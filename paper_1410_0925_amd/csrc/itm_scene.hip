@@ -178,7 +178,9 @@ itm_status make_geom(const itm_scene *sc, const itm_intrinsics *K, const double 
         g->tcw[i] = -acc;
     }
     g->s = (double)sc->s;
+    g->inv_s = 1.0 / g->s;
     g->inv_bs = 1.0 / (8.0 * g->s);
+    for (int c = 0; c < 3; c++) g->o_vox[c] = (float)(g->twc[c] / g->s);
     for (int j = 0; j < 3; j++)
         for (int a = 0; a < 3; a++) g->g[j][a] = (float)(g->Rcw[3 * a + j] * g->s);
     g->s_f = sc->s;
