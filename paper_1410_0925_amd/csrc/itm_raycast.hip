@@ -51,7 +51,7 @@ struct BlockReader {
         const int vx = (int)floorf(qx + 0.5f), vy = (int)floorf(qy + 0.5f), vz = (int)floorf(qz + 0.5f);
         const int32_t p = block(vx >> 3, vy >> 3, vz >> 3);
         if (p < 0) { F = 1.0f; return false; }
-        F = Vox<FMT>::to_f(sdf[(int64_t)p * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7)]);
+        F = Vox<FMT>::to_f(sdf[(int64_t)p * kBlockVox + (int32_t)((vx & 7) | (vy & 7) << 3 | (vz & 7) << 6)]);
         return true;
     }
 };
@@ -102,7 +102,7 @@ __device__ __forceinline__ float cube_F(const Cube<FMT> &cb, const typename Vox<
     const int32_t b0 = ey ? a1 : a0, b1 = ey ? a3 : a2;
     const int32_t ptr = ez ? b1 : b0;
     if (ptr < 0) return 1.0f;
-    return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7)]);
+    return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (int32_t)((vx & 7) | (vy & 7) << 3 | (vz & 7) << 6)]);
 }
 
 // the 8 lattice voxels of the cell with corner i
@@ -303,43 +303,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         float Fc[8];
         cube_cell(cb, sdf, ix, iy, iz, Fc);
         t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
-        // Second refinement: its cell and, speculatively, the normal stencil
-        // around it.  The final point nearly always stays in that cell; when it
-        // moves to a neighbouring cell, a second pass loads that cell's stencil.
-        // The neighbourhood is widened first to hold the stencils of the cell and
-        // of its 26 neighbours, so that no probe happens inside the loop; only the
-        // gradient leaves it.  (A final point farther away still gets the exact
-        // stencil, after the loop.)
+        // Second refinement in the cell j of the new point.  The neighbourhood is
+        // first widened to voxels [j - 2, j + 3], which holds the normal's stencil
+        // of j and of its 26 neighbours; the final point nearly always lies in one
+        // of those cells.
         qx = fmaf(t, dx, ox); qy = fmaf(t, dy, oy); qz = fmaf(t, dz, oz);
         fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
         ix = (int)fx; iy = (int)fy; iz = (int)fz;
         if (!cb.holds(ix - 2, iy - 2, iz - 2, ix + 3, iy + 3, iz + 3))
             cb.fetch(a.h, s_bfilt, ix - 2, iy - 2, iz - 2, ix + 3, iy + 3, iz + 3);
-        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-        bool done = false;
-        for (int pass = 0; pass < 2; pass++) {
-            if (pass == 1) {
-                fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
-                ix = (int)fx; iy = (int)fy; iz = (int)fz;
-                if (!cb.holds(ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2)) break;
-            }
-            float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
-            stencil(cb, sdf, ix, iy, iz, Fc, Ex, Ey, Ez);
-            if (pass == 0) {
-                t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
-                qx = fmaf(t, dx, ox); qy = fmaf(t, dy, oy); qz = fmaf(t, dz, oz);
-                if (floorf(qx) != fx || floorf(qy) != fy || floorf(qz) != fz) continue;
-            }
-            gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
-            done = true;
-            break;
-        }
-        if (!done) {   // the final point left the neighbourhood (rare)
+        cube_cell(cb, sdf, ix, iy, iz, Fc);
+        t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
+        // The normal: central differences of F_t over the stencil of the final
+        // point's cell (blocks fetched again only if that point moved farther)
+        qx = fmaf(t, dx, ox); qy = fmaf(t, dy, oy); qz = fmaf(t, dz, oz);
+        fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
+        ix = (int)fx; iy = (int)fy; iz = (int)fz;
+        if (!cb.holds(ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2))
             cb.fetch(a.h, s_bfilt, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
-            float Ex[2][4], Ey[2][4], Ez[2][4];
-            stencil(cb, sdf, ix, iy, iz, Fc, Ex, Ey, Ez);
-            gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
-        }
+        float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
+        stencil(cb, sdf, ix, iy, iz, Fc, Ex, Ey, Ez);
+        float gx, gy, gz;
+        gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
         // the hit in metres, (o + t d) s in binary64 from the march's binary32 terms
         P = make_float4((float)(g.s * ((double)ox + (double)t * (double)dx)),
                         (float)(g.s * ((double)oy + (double)t * (double)dy)),
