@@ -554,25 +554,40 @@ __device__ __forceinline__ TileBin tile_bin(const RangeBins &rb, int tx, int ty)
 // tile_bin.  Returns the empty range (+inf, 0) where no rectangle covers the
 // pixel.  A tile whose bin overflowed recomputes every visible block's
 // rectangle from the visible list.
-__device__ inline void tile_range(const FrameGeom &g, const VisList &list, const RangeBins &rb, int tx, int ty,
+__device__ __forceinline__ void tile_range(const FrameGeom &g, const VisList &list, const RangeBins &rb, int tx, int ty,
                                   const TileBin &bin, int u, int v, RangeLds &L, float &zlo, float &zhi)
 {
     const int tile = ty * rb.tw + tx;
-    const int n = bin.n;
+    const int n = __builtin_amdgcn_readfirstlane(bin.n);   // the same for every thread
     zlo = INFINITY;
     zhi = 0.0f;
     if (n <= rb.cap) {
         for (int base = 0; base < n; base += 256) {
             __syncthreads();
-            if (base + (int)threadIdx.x < n)
-                L.rect[threadIdx.x] = base == 0 ? bin.first : rb.rect[(int64_t)tile * rb.cap + base + threadIdx.x];
+            if (base + (int)threadIdx.x < n) {
+                // by value (a select between the two places would put bin in
+                // scratch memory)
+                RangeRect r = bin.first;
+                if (base != 0) r = rb.rect[(int64_t)tile * rb.cap + base + threadIdx.x];
+                L.rect[threadIdx.x] = r;
+            }
             __syncthreads();
             const int m = min(256, n - base);
-            for (int j = 0; j < m; j++) {
-                const RangeRect r = L.rect[j];
-                if (u >= r.u0 && u <= r.u1 && v >= r.v0 && v <= r.v1) {
-                    zlo = fminf(zlo, r.z0);
-                    zhi = fmaxf(zhi, r.z1);
+            // broadcast LDS reads of whole rectangles, four in flight at a time,
+            // tested without branches (depths are never NaN)
+            const uint4 *R = reinterpret_cast<const uint4 *>(L.rect);
+            int j = 0;
+            for (; j < m; j += 4) {
+                uint4 q[4];
+#pragma unroll
+                for (int k = 0; k < 4; k++) q[k] = R[min(j + k, m - 1)];
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    const bool in = (u >= (int)(int16_t)q[k].x) & (u <= ((int)q[k].x >> 16)) &
+                                    (v >= (int)(int16_t)q[k].y) & (v <= ((int)q[k].y >> 16));
+                    const float z0 = __uint_as_float(q[k].z), z1 = __uint_as_float(q[k].w);
+                    zlo = in & (z0 < zlo) ? z0 : zlo;
+                    zhi = in & (z1 > zhi) ? z1 : zhi;
                 }
             }
         }

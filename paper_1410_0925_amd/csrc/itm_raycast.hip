@@ -127,12 +127,14 @@ __device__ __forceinline__ float trilinear8(const float Fc[8], float rx, float r
 }
 
 // the cell with corner i and the outer layers of its 6 face neighbours: the
-// 32 voxels of the central differences of F_t at +- one voxel
+// 32 voxels of the central differences of F_t at +- one voxel (the cell's own 8
+// already in Fc when have_cell)
 template <int FMT>
 __device__ __forceinline__ void stencil(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int ix, int iy,
-                                        int iz, float Fc[8], float Ex[2][4], float Ey[2][4], float Ez[2][4])
+                                        int iz, bool have_cell, float Fc[8], float Ex[2][4], float Ey[2][4],
+                                        float Ez[2][4])
 {
-    cube_cell(cb, sdf, ix, iy, iz, Fc);
+    if (!have_cell) cube_cell(cb, sdf, ix, iy, iz, Fc);
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         const int a0 = k & 1, a1 = k >> 1;
@@ -183,10 +185,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     // the macro-cell and block filters, staged in LDS: empty-space tests cost an
     // LDS read (they are contiguous in global memory)
     __shared__ uint32_t s_filt[kMacroWords + kBlockFilterWords];
-    {
+    {   // all of a thread's reads issued before its LDS writes: one round trip
+        constexpr int kPer = (kMacroWords + kBlockFilterWords) / 4 / 256;
+        static_assert(kPer * 4 * 256 == kMacroWords + kBlockFilterWords, "filters fill whole 256-thread rounds");
         const uint4 *src = reinterpret_cast<const uint4 *>(a.h.macro);
         uint4 *dst = reinterpret_cast<uint4 *>(s_filt);
-        for (int i = threadIdx.x; i < (kMacroWords + kBlockFilterWords) / 4; i += blockDim.x) dst[i] = src[i];
+        uint4 w[kPer];
+#pragma unroll
+        for (int k = 0; k < kPer; k++) w[k] = src[threadIdx.x + 256 * k];
+#pragma unroll
+        for (int k = 0; k < kPer; k++) dst[threadIdx.x + 256 * k] = w[k];
     }
     __syncthreads();
     const uint32_t *s_macro = s_filt;
@@ -307,12 +315,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         // first widened to voxels [j - 2, j + 3], which holds the normal's stencil
         // of j and of its 26 neighbours; the final point nearly always lies in one
         // of those cells.
+        // A lane whose point stays in its cell keeps the cell's voxels (fewer
+        // gathers for the wave's memory pipeline, which bounds this kernel).
         qx = fmaf(t, dx, ox); qy = fmaf(t, dy, oy); qz = fmaf(t, dz, oz);
         fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
-        ix = (int)fx; iy = (int)fy; iz = (int)fz;
-        if (!cb.holds(ix - 2, iy - 2, iz - 2, ix + 3, iy + 3, iz + 3))
-            cb.fetch(a.h, s_bfilt, ix - 2, iy - 2, iz - 2, ix + 3, iy + 3, iz + 3);
-        cube_cell(cb, sdf, ix, iy, iz, Fc);
+        int jx = (int)fx, jy = (int)fy, jz = (int)fz;
+        if (!cb.holds(jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3))
+            cb.fetch(a.h, s_bfilt, jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3);
+        if (jx != ix || jy != iy || jz != iz) cube_cell(cb, sdf, jx, jy, jz, Fc);
         t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
         // The normal: central differences of F_t over the stencil of the final
         // point's cell (blocks fetched again only if that point moved farther)
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         if (!cb.holds(ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2))
             cb.fetch(a.h, s_bfilt, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
         float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
-        stencil(cb, sdf, ix, iy, iz, Fc, Ex, Ey, Ez);
+        stencil(cb, sdf, ix, iy, iz, ix == jx && iy == jy && iz == jz, Fc, Ex, Ey, Ez);
         float gx, gy, gz;
         gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
         // the hit in metres, (o + t d) s in binary64 from the march's binary32 terms
