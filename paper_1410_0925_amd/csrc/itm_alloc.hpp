@@ -128,41 +128,9 @@ __device__ __forceinline__ bool set_insert(int32_t *s_e, unsigned long long *s_k
 // the 8 lanes then takes every 8th tile, so the reservations go out together.
 __device__ inline void bin_blocks(const FrameGeom &g, const RangeBins &rb, const unsigned long long *keys, int n)
 {
-    const int grp = threadIdx.x >> 3, corner = threadIdx.x & 7;
     for (int base = 0; base < n; base += 32) {   // uniform
-        const int j = base + grp;
-        BoxAcc b;
-        if (j < n) {
-            int kx, ky, kz;
-            unpack_key(keys[j], kx, ky, kz);
-            box_corner(g, kx, ky, kz, corner, b);
-        } else {
-            b.zlo = b.xlo = b.ylo = INFINITY;
-            b.zhi = b.xhi = b.yhi = -INFINITY;
-            b.behind = false;
-        }
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) {
-            BoxAcc c;
-            c.zlo = __shfl_xor(b.zlo, o, kWave);
-            c.zhi = __shfl_xor(b.zhi, o, kWave);
-            c.xlo = __shfl_xor(b.xlo, o, kWave);
-            c.xhi = __shfl_xor(b.xhi, o, kWave);
-            c.ylo = __shfl_xor(b.ylo, o, kWave);
-            c.yhi = __shfl_xor(b.yhi, o, kWave);
-            c.behind = __shfl_xor((int)b.behind, o, kWave) != 0;
-            box_merge(b, c);
-        }
-        RangeRect r;
-        if (j < n && box_rect(g, b, r)) {
-            int tx0, ty0, ntx, n_tiles;
-            rect_tiles(r, tx0, ty0, ntx, n_tiles);
-            for (int t = corner; t < n_tiles; t += 8) {
-                const int tile = (ty0 + t / ntx) * rb.tw + tx0 + t % ntx;
-                const int slot = atomicAdd(&rb.cnt[tile], 1);
-                if (slot < rb.cap) rb.rect[(int64_t)tile * rb.cap + slot] = r;
-            }
-        }
+        const int j = base + (int)(threadIdx.x >> 3);
+        bin_block8(g, rb, j < n, j < n ? keys[j] : 0ull);
     }
 }
 

@@ -478,6 +478,48 @@ __device__ __forceinline__ void rect_tiles(const RangeRect &r, int &tx0, int &ty
     n = ntx * (r.v1 / kTile - ty0 + 1);
 }
 
+// One block's rectangle appended to the bins of the tiles it overlaps by a group
+// of 8 consecutive lanes: lane c = lane & 7 projects box corner c, a butterfly
+// merges the 8, then lane c takes every 8th tile, so the reservations go out
+// together.  valid is uniform over the group.
+__device__ __forceinline__ void bin_block8(const FrameGeom &g, const RangeBins &rb, bool valid,
+                                           unsigned long long key)
+{
+    const int corner = threadIdx.x & 7;
+    BoxAcc b;
+    if (valid) {
+        int kx, ky, kz;
+        unpack_key(key, kx, ky, kz);
+        box_corner(g, kx, ky, kz, corner, b);
+    } else {
+        b.zlo = b.xlo = b.ylo = INFINITY;
+        b.zhi = b.xhi = b.yhi = -INFINITY;
+        b.behind = false;
+    }
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+        BoxAcc c;
+        c.zlo = __shfl_xor(b.zlo, o, kWave);
+        c.zhi = __shfl_xor(b.zhi, o, kWave);
+        c.xlo = __shfl_xor(b.xlo, o, kWave);
+        c.xhi = __shfl_xor(b.xhi, o, kWave);
+        c.ylo = __shfl_xor(b.ylo, o, kWave);
+        c.yhi = __shfl_xor(b.yhi, o, kWave);
+        c.behind = __shfl_xor((int)b.behind, o, kWave) != 0;
+        box_merge(b, c);
+    }
+    RangeRect r;
+    if (valid && box_rect(g, b, r)) {
+        int tx0, ty0, ntx, n_tiles;
+        rect_tiles(r, tx0, ty0, ntx, n_tiles);
+        for (int t = corner; t < n_tiles; t += 8) {
+            const int tile = (ty0 + t / ntx) * rb.tw + tx0 + t % ntx;
+            const int slot = atomicAdd(&rb.cnt[tile], 1);
+            if (slot < rb.cap) rb.rect[(int64_t)tile * rb.cap + slot] = r;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // visible-list access
 // ---------------------------------------------------------------------------

@@ -33,18 +33,10 @@ __global__ __launch_bounds__(256) void k_range_bin(FrameGeom g, VisList list, Ra
     }
     __syncthreads();
     const int total = s_pre[kListSegs];
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-        int kx, ky, kz;
-        unpack_key(vis_item_at(list, s_pre, i).key, kx, ky, kz);
-        RangeRect r;
-        if (!block_rect(g, kx, ky, kz, r)) continue;
-        int tx0, ty0, ntx, n;
-        rect_tiles(r, tx0, ty0, ntx, n);
-        for (int t = 0; t < n; t++) {
-            const int tile = (ty0 + t / ntx) * rb.tw + tx0 + t % ntx;
-            const int slot = atomicAdd(&rb.cnt[tile], 1);
-            if (slot < rb.cap) rb.rect[(int64_t)tile * rb.cap + slot] = r;
-        }
+    // 32 blocks per workgroup pass, 8 lanes each
+    for (int base = blockIdx.x * 32; base < total; base += gridDim.x * 32) {   // uniform
+        const int j = base + (int)(threadIdx.x >> 3);
+        bin_block8(g, rb, j < total, j < total ? vis_item_at(list, s_pre, j).key : 0ull);
     }
 }
 
