@@ -35,15 +35,15 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 #   --no-cpu-baseline --no-learned --no-events --calib-copy-mb 256
 # (summaries under profiles/).  FETCH_SIZE counts 64 B per read request while
 # these kernels' read requests are 128 B (TCC_EA0_RDREQ_128B): the reference
-# elementwise kernel that reads 256 MiB reports 131,090 KiB, hence the factor 2;
+# elementwise kernel that reads 256 MiB reports 131,088 KiB, hence the factor 2;
 # WRITE_SIZE reports the 256 MiB it writes exactly.  `src` is a SHA-256 prefix of
 # the kernel's source files when the counters were taken; a changed kernel
 # reports traffic null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131089.8, 262144.0 / 262144.0
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.7, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga"): {"fetch": 1021.8, "write": 1204.7, "src": "0730dadb3031ee60"},
-    ("integrate", "f32", "vga"): {"fetch": 10010.5, "write": 14770.6, "src": "0730dadb3031ee60"},
-    ("raycast", "f32", "vga"): {"fetch": 5224.6, "write": 9600.0, "src": "cb54ff4904f5b982"},
+    ("alloc", "f32", "vga"): {"fetch": 1022.1, "write": 1207.8, "src": "f2aca75d3affc467"},
+    ("integrate", "f32", "vga"): {"fetch": 10012.6, "write": 14770.7, "src": "f2aca75d3affc467"},
+    ("raycast", "f32", "vga"): {"fetch": 7215.7, "write": 9600.0, "src": "dd70aba0ca6d4eda"},
 }
 
 
