@@ -110,9 +110,13 @@ __device__ __forceinline__ bool in_key_range(int x, int y, int z)
 
 // hashIndex of section "Hash Table and Hashing Function": unsigned 32-bit products
 // of the coordinates with three primes, xor-ed, masked to the bucket count
+__device__ __forceinline__ uint32_t hash_raw(int x, int y, int z)
+{
+    return ((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u);
+}
 __device__ __forceinline__ uint32_t hash_index(int x, int y, int z, uint32_t mask)
 {
-    return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349669u) ^ ((uint32_t)z * 83492791u)) & mask;
+    return hash_raw(x, y, z) & mask;
 }
 
 // the bucket's two entries, then (both taken) the excess chain; returns the
@@ -374,8 +378,9 @@ __device__ __forceinline__ uint32_t macro_index(int bx, int by, int bz)
 }
 __device__ __forceinline__ uint32_t bfilt_index(int bx, int by, int bz)
 {
-    // a different mix from hashIndex, so that filter and bucket collisions are independent
-    return ((uint32_t)bx * 2654435761u ^ (uint32_t)by * 2246822519u ^ (uint32_t)bz * 3266489917u) >> 15;
+    // the low bits of the bucket hash: a test followed by a probe of the same
+    // block computes the products once
+    return hash_index(bx, by, bz, kBlockFilterBits - 1);
 }
 
 // retrieval without the bucket bitmap, for blocks that are probably allocated
@@ -383,6 +388,16 @@ __device__ __forceinline__ int32_t find_block_direct(const HashView &h, int x, i
 {
     if (!in_key_range(x, y, z)) return -1;
     return probe_bucket(h, hash_index(x, y, z, h.mask), pack_key(x, y, z));
+}
+
+// retrieval behind the block filter (filt: the filter's words, e.g. staged in
+// LDS): -1 without a probe when the filter proves the block absent
+__device__ __forceinline__ int32_t find_block_filtered(const HashView &h, const uint32_t *filt, int x, int y, int z)
+{
+    const uint32_t hr = hash_raw(x, y, z);
+    const uint32_t fi = hr & (kBlockFilterBits - 1);
+    if (!((filt[fi >> 5] >> (fi & 31)) & 1u) || !in_key_range(x, y, z)) return -1;
+    return probe_bucket(h, hr & h.mask, pack_key(x, y, z));
 }
 
 // key of hash entry e (entry ids as in the layout above); the block is e itself

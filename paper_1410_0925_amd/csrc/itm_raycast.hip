@@ -40,8 +40,7 @@ struct BlockReader {
     {
         if (bx != cx || by != cy || bz != cz) {
             cx = bx; cy = by; cz = bz;
-            const uint32_t fi = bfilt_index(bx, by, bz);
-            cptr = ((filt[fi >> 5] >> (fi & 31)) & 1u) ? find_block_direct(h, bx, by, bz) : -1;
+            cptr = find_block_filtered(h, filt, bx, by, bz);
         }
         return cptr;
     }
@@ -84,9 +83,7 @@ struct Cube {
             const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
             const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
             const int kx = dx ? bx1 : bx0, ky = dy ? by1 : by0, kz = dz ? bz1 : bz0;
-            const uint32_t fi = bfilt_index(kx, ky, kz);
-            const bool maybe = (filt[fi >> 5] >> (fi & 31)) & 1u;
-            p[c] = need && maybe ? find_block_direct(h, kx, ky, kz) : -1;
+            p[c] = need ? find_block_filtered(h, filt, kx, ky, kz) : -1;
         }
     }
 };
