@@ -71,6 +71,11 @@ def lib():
             "orc_raycast_crossing": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
             "orc_expected_depths": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
             "orc_num_threads": (C.c_int, []),
+            "orc_depth_level": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, _P]),
+            "orc_icp_system": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, _P, _P, _P, C.c_double, _P]),
+            "orc_solve6": (C.c_int, [_P, _P, _P]),
+            "orc_pose_step": (None, [_P, _P]),
+            "orc_track": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, C.c_int, _P, _P, C.c_int, _P, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -251,6 +256,69 @@ class Dense:
         fr = np.empty((nz, ny, nx), np.uint64)
         lib().orc_dense_read(self.h, _ptr(F), _ptr(Wt), _ptr(fr))
         return F, Wt, fr
+
+
+# -- depth tracker (section "Tracking") --------------------------------------
+
+def depth_level(depth, level):
+    """Level `level` of the depth hierarchy (binary64; 0 where no valid depth)."""
+    d = np.ascontiguousarray(depth, np.float32)
+    H, W = d.shape
+    out = np.empty(W * H, np.float64)
+    wl, hl = C.c_int(), C.c_int()
+    if lib().orc_depth_level(_ptr(d), W, H, level, _ptr(out), C.byref(wl), C.byref(hl)):
+        raise MemoryError
+    return out[: wl.value * hl.value].reshape(hl.value, wl.value)
+
+
+def _maps(V, N, H, W):
+    V = np.ascontiguousarray(V, np.float32)
+    N = np.ascontiguousarray(N, np.float32)
+    assert V.shape == (H, W, 4) and N.shape == (H, W, 4)
+    return V, N
+
+
+def icp_system(depth, intr, level, V, N, T_ref, T, dist_thresh):
+    """The 29 sums of one Gauss-Newton step: upper triangle of A (21), g (6),
+    sum of squared distances, number of pairs."""
+    d = np.ascontiguousarray(depth, np.float32)
+    H, W = d.shape
+    V, N = _maps(V, N, H, W)
+    sys_ = np.empty(29, np.float64)
+    lib().orc_icp_system(_ptr(d), W, H, _ptr(_K(intr)), level, _ptr(V), _ptr(N),
+                         _ptr(np.ascontiguousarray(T_ref, np.float64)),
+                         _ptr(np.ascontiguousarray(T, np.float64)), float(dist_thresh), _ptr(sys_))
+    return sys_
+
+
+def solve6(A_up, b):
+    x = np.empty(6, np.float64)
+    if lib().orc_solve6(_ptr(np.ascontiguousarray(A_up, np.float64)), _ptr(np.ascontiguousarray(b, np.float64)),
+                        _ptr(x)):
+        raise np.linalg.LinAlgError("not positive definite")
+    return x
+
+
+def pose_step(xi, T):
+    T = np.array(T, np.float64, copy=True, order="C")
+    lib().orc_pose_step(_ptr(np.ascontiguousarray(xi, np.float64)), _ptr(T))
+    return T
+
+
+def track(depth, intr, V, N, T_ref, T_init, iters=(4, 6, 10), dist=(0.02, 0.05, 0.1), min_inliers=100):
+    """Point-to-plane tracking over len(iters) levels (finest first).  Returns
+    (T [4,4], info {pairs, rms, steps})."""
+    d = np.ascontiguousarray(depth, np.float32)
+    H, W = d.shape
+    V, N = _maps(V, N, H, W)
+    it = np.ascontiguousarray(iters, np.int32)
+    ds = np.ascontiguousarray(dist, np.float64)
+    T = np.empty((4, 4), np.float64)
+    info = np.empty(3, np.float64)
+    lib().orc_track(_ptr(d), W, H, _ptr(_K(intr)), _ptr(V), _ptr(N), _ptr(np.ascontiguousarray(T_ref, np.float64)),
+                    _ptr(np.ascontiguousarray(T_init, np.float64)), len(it), _ptr(it), _ptr(ds), int(min_inliers),
+                    _ptr(T), _ptr(info))
+    return T, {"pairs": int(info[0]), "rms": float(info[1]), "steps": int(info[2])}
 
 
 def num_threads() -> int:

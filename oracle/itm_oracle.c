@@ -28,6 +28,8 @@
  *   raycast state machine ................ section "Raycast"
  *   expected depth range per pixel ....... section "Raycast" (search range,
  *                                          CreateExpectedDepths)
+ *   depth tracker (point-to-plane ICP over
+ *     a resolution hierarchy) ............ section "Tracking" (ITMDepthTracker)
  * Readings where the paper is silent are noted beside the code that takes them.
  */
 #include <math.h>
@@ -1072,6 +1074,229 @@ int orc_expected_depths(const orc_scene *sc, int W, int H, const double *K, cons
                 if (fz1 > r[1]) r[1] = fz1;
             }
     }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* depth tracker, section "Tracking" (ITMDepthTracker): the reference maps V   */
+/* (surface points) and N (normals), world frame, come from a raycast at pose  */
+/* T_ref with intrinsics K at full resolution; every point p of the new depth  */
+/* image, moved by the current estimate T (camera -> world), is projected into */
+/* the reference view, paired with the nearest reference pixel, and scored by  */
+/* its distance to the plane there, d = (T p - V)^T N.  A Gauss-Newton step     */
+/* solves the linearised least squares; levels of a resolution hierarchy are   */
+/* visited coarse to fine.  binary64 throughout.                               */
+/* Readings (the paper gives the scheme, not these details):                   */
+/*   hierarchy: level l halves level l - 1 (W_l = W_{l-1} / 2, floor); a pixel  */
+/*     is the mean of the valid (finite, > 0) depths of its 2 x 2 parents, 0    */
+/*     when none is valid; intrinsics fx / 2^l, fy / 2^l, (cx + 1/2) / 2^l - 1/2 */
+/*     (pixel centres at integer coordinates on every level);                   */
+/*   pairing: nearest reference pixel floor(x + 1/2), floor(y + 1/2) of the     */
+/*     projection with the full-resolution K; a pair counts when both maps are  */
+/*     valid there (w > 0) and |T p - V| <= the level's distance threshold;     */
+/*   linearisation: T <- (exp([w]x), v) T, so d(w, v) ~ d + w.(P x N) + v.N at  */
+/*     P = T p: J = (P x N, N);  A = sum J J^T, g = sum J d, step A x = -g      */
+/*     (Cholesky); the rotation exp by Rodrigues' formula;                      */
+/*   a level stops early when fewer than min_inliers pairs remain.             */
+/* ------------------------------------------------------------------------- */
+
+/* level l of the depth hierarchy (level 0 = the input, as binary64) */
+int orc_depth_level(const float *depth, int W, int H, int level, double *out, int *Wl, int *Hl)
+{
+    int w = W, h = H;
+    double *cur = malloc(sizeof(double) * (size_t)W * H);
+    double *nxt = malloc(sizeof(double) * (size_t)W * H);
+    if (!cur || !nxt) { free(cur); free(nxt); return -1; }
+    for (int64_t i = 0; i < (int64_t)W * H; i++) {
+        const double d = depth[i];
+        cur[i] = (isfinite(d) && d > 0.0) ? d : 0.0;
+    }
+    for (int l = 1; l <= level; l++) {
+        const int w2 = w / 2, h2 = h / 2;
+        for (int v = 0; v < h2; v++)
+            for (int u = 0; u < w2; u++) {
+                double sum = 0.0;
+                int n = 0;
+                for (int dv = 0; dv < 2; dv++)
+                    for (int du = 0; du < 2; du++) {
+                        const double d = cur[(int64_t)(2 * v + dv) * w + (2 * u + du)];
+                        if (d > 0.0) { sum += d; n++; }
+                    }
+                nxt[(int64_t)v * w2 + u] = n ? sum / n : 0.0;
+            }
+        double *tmp = cur; cur = nxt; nxt = tmp;
+        w = w2;
+        h = h2;
+    }
+    for (int64_t i = 0; i < (int64_t)w * h; i++) out[i] = cur[i];
+    *Wl = w;
+    *Hl = h;
+    free(cur);
+    free(nxt);
+    return 0;
+}
+
+static void orc_pose_parts(const double *T, double R[9], double t[3])
+{
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) R[3 * i + j] = T[4 * i + j];
+        t[i] = T[4 * i + 3];
+    }
+}
+
+/* sums of one Gauss-Newton step at pose T on hierarchy level `level`:
+   sys[0..20] upper triangle of A row by row, sys[21..26] g, sys[27] sum d^2,
+   sys[28] number of pairs */
+static void orc_icp_sums(const double *dl, int Wl, int Hl, int level, int W, int H, const double *K,
+                         const float *V, const float *N, const double *T_ref, const double *T,
+                         double dist_thresh, double *sys)
+{
+    const double sc = ldexp(1.0, -level);
+    const double fxl = K[0] * sc, fyl = K[1] * sc;
+    const double cxl = (K[2] + 0.5) * sc - 0.5, cyl = (K[3] + 0.5) * sc - 0.5;
+    double R[9], t[3], Rr[9], tr[3];
+    orc_pose_parts(T, R, t);
+    orc_pose_parts(T_ref, Rr, tr);
+    for (int i = 0; i < 29; i++) sys[i] = 0.0;
+    for (int v = 0; v < Hl; v++)
+        for (int u = 0; u < Wl; u++) {
+            const double d = dl[(int64_t)v * Wl + u];
+            if (!(d > 0.0)) continue;
+            const double p[3] = {d * (u - cxl) / fxl, d * (v - cyl) / fyl, d};
+            double P[3], X[3];
+            for (int a = 0; a < 3; a++) P[a] = R[3 * a] * p[0] + R[3 * a + 1] * p[1] + R[3 * a + 2] * p[2] + t[a];
+            /* into the reference camera: R_ref^T (P - t_ref) */
+            for (int a = 0; a < 3; a++)
+                X[a] = Rr[a] * (P[0] - tr[0]) + Rr[3 + a] * (P[1] - tr[1]) + Rr[6 + a] * (P[2] - tr[2]);
+            if (!(X[2] > 0.0)) continue;
+            const double x = K[0] * X[0] / X[2] + K[2], y = K[1] * X[1] / X[2] + K[3];
+            const double xf = floor(x + 0.5), yf = floor(y + 0.5);
+            if (!(xf >= 0.0 && xf <= W - 1 && yf >= 0.0 && yf <= H - 1)) continue;
+            const int64_t q = (int64_t)yf * W + (int64_t)xf;
+            const float *Vq = V + 4 * q, *Nq = N + 4 * q;
+            if (!(Vq[3] > 0.0f) || !(Nq[3] > 0.0f)) continue;
+            const double diff[3] = {P[0] - Vq[0], P[1] - Vq[1], P[2] - Vq[2]};
+            if (sqrt(diff[0] * diff[0] + diff[1] * diff[1] + diff[2] * diff[2]) > dist_thresh) continue;
+            const double n[3] = {Nq[0], Nq[1], Nq[2]};
+            const double r = diff[0] * n[0] + diff[1] * n[1] + diff[2] * n[2];
+            const double J[6] = {P[1] * n[2] - P[2] * n[1], P[2] * n[0] - P[0] * n[2], P[0] * n[1] - P[1] * n[0],
+                                 n[0], n[1], n[2]};
+            int k = 0;
+            for (int i = 0; i < 6; i++)
+                for (int j = i; j < 6; j++) sys[k++] += J[i] * J[j];
+            for (int i = 0; i < 6; i++) sys[21 + i] += J[i] * r;
+            sys[27] += r * r;
+            sys[28] += 1.0;
+        }
+}
+
+int orc_icp_system(const float *depth, int W, int H, const double *K, int level, const float *V,
+                   const float *N, const double *T_ref, const double *T, double dist_thresh, double *sys)
+{
+    double *dl = malloc(sizeof(double) * (size_t)W * H);
+    int Wl, Hl;
+    if (!dl || orc_depth_level(depth, W, H, level, dl, &Wl, &Hl)) { free(dl); return -1; }
+    orc_icp_sums(dl, Wl, Hl, level, W, H, K, V, N, T_ref, T, dist_thresh, sys);
+    free(dl);
+    return 0;
+}
+
+/* solve A x = b, A symmetric positive definite (upper triangle packed row by
+   row), by Cholesky; returns -1 when A is not positive definite */
+int orc_solve6(const double *Aup, const double *b, double *x)
+{
+    double A[36], L[36] = {0}, y[6];
+    int k = 0;
+    for (int i = 0; i < 6; i++)
+        for (int j = i; j < 6; j++) { A[6 * i + j] = Aup[k]; A[6 * j + i] = Aup[k]; k++; }
+    for (int j = 0; j < 6; j++) {
+        double s = A[6 * j + j];
+        for (int m = 0; m < j; m++) s -= L[6 * j + m] * L[6 * j + m];
+        if (!(s > 0.0)) return -1;
+        L[6 * j + j] = sqrt(s);
+        for (int i = j + 1; i < 6; i++) {
+            double r = A[6 * i + j];
+            for (int m = 0; m < j; m++) r -= L[6 * i + m] * L[6 * j + m];
+            L[6 * i + j] = r / L[6 * j + j];
+        }
+    }
+    for (int i = 0; i < 6; i++) {
+        double s = b[i];
+        for (int m = 0; m < i; m++) s -= L[6 * i + m] * y[m];
+        y[i] = s / L[6 * i + i];
+    }
+    for (int i = 5; i >= 0; i--) {
+        double s = y[i];
+        for (int m = i + 1; m < 6; m++) s -= L[6 * m + i] * x[m];
+        x[i] = s / L[6 * i + i];
+    }
+    return 0;
+}
+
+/* T <- (exp([w]x), v) T, the rotation by Rodrigues' formula */
+void orc_pose_step(const double *xi, double *T)
+{
+    const double w[3] = {xi[0], xi[1], xi[2]};
+    const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    double Rinc[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (th > 0.0) {
+        const double k[3] = {w[0] / th, w[1] / th, w[2] / th};
+        const double c = cos(th), s = sin(th), C1 = 1.0 - c;
+        const double Kx[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+        for (int i = 0; i < 3; i++)
+            for (int j = 0; j < 3; j++) {
+                double kk = 0.0;
+                for (int m = 0; m < 3; m++) kk += Kx[3 * i + m] * Kx[3 * m + j];
+                Rinc[3 * i + j] = (i == j ? 1.0 : 0.0) + s * Kx[3 * i + j] + C1 * kk;
+            }
+    }
+    double R[9], t[3], Rn[9], tn[3];
+    orc_pose_parts(T, R, t);
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) {
+            double acc = 0.0;
+            for (int m = 0; m < 3; m++) acc += Rinc[3 * i + m] * R[3 * m + j];
+            Rn[3 * i + j] = acc;
+        }
+        tn[i] = Rinc[3 * i] * t[0] + Rinc[3 * i + 1] * t[1] + Rinc[3 * i + 2] * t[2] + xi[3 + i];
+    }
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) T[4 * i + j] = Rn[3 * i + j];
+        T[4 * i + 3] = tn[i];
+    }
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+}
+
+/* the tracker: levels n_levels - 1 .. 0, iters[l] Gauss-Newton steps on level
+   l with distance threshold dist[l]; info = {pairs of the last system,
+   RMS distance of the last system, steps taken} */
+int orc_track(const float *depth, int W, int H, const double *K, const float *V, const float *N,
+              const double *T_ref, const double *T_init, int n_levels, const int *iters,
+              const double *dist, int min_inliers, double *T_out, double *info)
+{
+    double *dl = malloc(sizeof(double) * (size_t)W * H);
+    if (!dl) return -1;
+    for (int i = 0; i < 16; i++) T_out[i] = T_init[i];
+    double sys[29] = {0};
+    int steps = 0;
+    for (int l = n_levels - 1; l >= 0; l--) {
+        int Wl, Hl;
+        orc_depth_level(depth, W, H, l, dl, &Wl, &Hl);
+        for (int it = 0; it < iters[l]; it++) {
+            orc_icp_sums(dl, Wl, Hl, l, W, H, K, V, N, T_ref, T_out, dist[l], sys);
+            if (sys[28] < min_inliers) break;
+            double b[6], xi[6];
+            for (int i = 0; i < 6; i++) b[i] = -sys[21 + i];
+            if (orc_solve6(sys, b, xi)) break;
+            orc_pose_step(xi, T_out);
+            steps++;
+        }
+    }
+    info[0] = sys[28];
+    info[1] = sys[28] > 0 ? sqrt(sys[27] / sys[28]) : 0.0;
+    info[2] = steps;
+    free(dl);
     return 0;
 }
 

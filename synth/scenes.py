@@ -224,6 +224,38 @@ def render_depth(scene: Scene, intrinsics, width: int, height: int, T_wc: np.nda
     return t
 
 
+def render_plane_maps(planes, intrinsics, width: int, height: int, T_wc: np.ndarray):
+    """Reference maps of a scene of planes (rows n_x, n_y, n_z, c: the plane
+    n . x = c, hit from the side its unit normal faces): camera-z of the first hit
+    per pixel (float64 [H, W], 0 = no hit), and the hit's world point and normal
+    as float32 [H, W, 4] with w = 1 (all zero on a miss)."""
+    planes = np.asarray(planes, np.float64)
+    fx, fy, cx, cy = intrinsics
+    xs = (np.arange(width, dtype=np.float64) - cx) / fx
+    ys = (np.arange(height, dtype=np.float64) - cy) / fy
+    R, o = T_wc[:3, :3], T_wc[:3, 3]
+    d = np.stack([R[a, 0] * xs[None, :] + R[a, 1] * ys[:, None] + R[a, 2] for a in range(3)], -1)
+    t = np.full((height, width), np.inf)
+    idx = np.full((height, width), -1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for i, pl in enumerate(planes):
+            den = d @ pl[:3]
+            th = (pl[3] - o @ pl[:3]) / den
+            hit = (den < 0) & (th > 0) & (th < t)
+            t[hit] = th[hit]
+            idx[hit] = i
+    hit = idx >= 0
+    depth = np.where(hit, t, 0.0)   # camera z: the direction has camera-z 1
+    V = np.zeros((height, width, 4), np.float32)
+    N = np.zeros((height, width, 4), np.float32)
+    P = o + d * np.where(hit, t, 0.0)[..., None]
+    V[..., :3] = np.where(hit[..., None], P, 0.0)
+    V[..., 3] = hit
+    N[..., :3] = np.where(hit[..., None], planes[np.maximum(idx, 0), :3], 0.0)
+    N[..., 3] = hit
+    return depth, V, N
+
+
 def _sensor(z: np.ndarray, rng, noise: bool, invalid_frac: float) -> np.ndarray:
     z = z.copy()
     if noise:
