@@ -1087,10 +1087,13 @@ int orc_expected_depths(const orc_scene *sc, int W, int H, const double *K, cons
 /* solves the linearised least squares; levels of a resolution hierarchy are   */
 /* visited coarse to fine.  binary64 throughout.                               */
 /* Readings (the paper gives the scheme, not these details):                   */
-/*   hierarchy: level l halves level l - 1 (W_l = W_{l-1} / 2, floor); a pixel  */
-/*     is the mean of the valid (finite, > 0) depths of its 2 x 2 parents, 0    */
-/*     when none is valid; intrinsics fx / 2^l, fy / 2^l, (cx + 1/2) / 2^l - 1/2 */
-/*     (pixel centres at integer coordinates on every level);                   */
+/*   hierarchy: level l keeps every other pixel of level l - 1 in each        */
+/*     direction (pixel (u, v) of level l is pixel (2u, 2v) of level l - 1,     */
+/*     W_l = ceil(W_{l-1} / 2)), so it is pixel (2^l u, 2^l v) of the input,    */
+/*     with intrinsics fx / 2^l, fy / 2^l, cx / 2^l, cy / 2^l.  (A 2 x 2 mean   */
+/*     would sit at the half-pixel between four input pixels: at the reference */
+/*     pose every coarse point would then project exactly between two          */
+/*     reference pixels, and the pairing would be decided by rounding.)        */
 /*   pairing: nearest reference pixel floor(x + 1/2), floor(y + 1/2) of the     */
 /*     projection with the full-resolution K; a pair counts when both maps are  */
 /*     valid there (w > 0) and |T p - V| <= the level's distance threshold;     */
@@ -1103,36 +1106,15 @@ int orc_expected_depths(const orc_scene *sc, int W, int H, const double *K, cons
 /* level l of the depth hierarchy (level 0 = the input, as binary64) */
 int orc_depth_level(const float *depth, int W, int H, int level, double *out, int *Wl, int *Hl)
 {
-    int w = W, h = H;
-    double *cur = malloc(sizeof(double) * (size_t)W * H);
-    double *nxt = malloc(sizeof(double) * (size_t)W * H);
-    if (!cur || !nxt) { free(cur); free(nxt); return -1; }
-    for (int64_t i = 0; i < (int64_t)W * H; i++) {
-        const double d = depth[i];
-        cur[i] = (isfinite(d) && d > 0.0) ? d : 0.0;
-    }
-    for (int l = 1; l <= level; l++) {
-        const int w2 = w / 2, h2 = h / 2;
-        for (int v = 0; v < h2; v++)
-            for (int u = 0; u < w2; u++) {
-                double sum = 0.0;
-                int n = 0;
-                for (int dv = 0; dv < 2; dv++)
-                    for (int du = 0; du < 2; du++) {
-                        const double d = cur[(int64_t)(2 * v + dv) * w + (2 * u + du)];
-                        if (d > 0.0) { sum += d; n++; }
-                    }
-                nxt[(int64_t)v * w2 + u] = n ? sum / n : 0.0;
-            }
-        double *tmp = cur; cur = nxt; nxt = tmp;
-        w = w2;
-        h = h2;
-    }
-    for (int64_t i = 0; i < (int64_t)w * h; i++) out[i] = cur[i];
+    const int step = 1 << level;
+    const int w = (W + step - 1) / step, h = (H + step - 1) / step;
+    for (int v = 0; v < h; v++)
+        for (int u = 0; u < w; u++) {
+            const double d = depth[(int64_t)(v * step) * W + (int64_t)u * step];
+            out[(int64_t)v * w + u] = (isfinite(d) && d > 0.0) ? d : 0.0;
+        }
     *Wl = w;
     *Hl = h;
-    free(cur);
-    free(nxt);
     return 0;
 }
 
@@ -1152,8 +1134,7 @@ static void orc_icp_sums(const double *dl, int Wl, int Hl, int level, int W, int
                          double dist_thresh, double *sys)
 {
     const double sc = ldexp(1.0, -level);
-    const double fxl = K[0] * sc, fyl = K[1] * sc;
-    const double cxl = (K[2] + 0.5) * sc - 0.5, cyl = (K[3] + 0.5) * sc - 0.5;
+    const double fxl = K[0] * sc, fyl = K[1] * sc, cxl = K[2] * sc, cyl = K[3] * sc;
     double R[9], t[3], Rr[9], tr[3];
     orc_pose_parts(T, R, t);
     orc_pose_parts(T_ref, Rr, tr);

@@ -41,17 +41,13 @@ def test_depth_level_brute_force():
     d[rng.random(d.shape) < 0.3] = 0.0
     d[rng.random(d.shape) < 0.05] = np.nan
     d[rng.random(d.shape) < 0.05] = np.inf
-    cur = np.where(np.isfinite(d) & (d > 0), d.astype(np.float64), 0.0)
-    assert np.array_equal(oracle.depth_level(d, 0), cur)
-    for level in (1, 2, 3):
-        h, w = cur.shape[0] // 2, cur.shape[1] // 2
-        q = cur[: 2 * h, : 2 * w].reshape(h, 2, w, 2)
-        n = (q > 0).sum(axis=(1, 3))
-        s = q.sum(axis=(1, 3))
-        cur = np.where(n > 0, s / np.maximum(n, 1), 0.0)
+    d[rng.random(d.shape) < 0.05] = -1.0
+    clean = np.where(np.isfinite(d) & (d > 0), d.astype(np.float64), 0.0)
+    for level in (0, 1, 2, 3):
+        want = clean[:: 1 << level, :: 1 << level]
         got = oracle.depth_level(d, level)
-        assert got.shape == cur.shape
-        np.testing.assert_allclose(got, cur, rtol=1e-15, atol=0)
+        assert got.shape == want.shape == (-(-61 // (1 << level)), -(-83 // (1 << level)))
+        assert np.array_equal(got, want)
 
 
 def test_solve6_against_numpy():
@@ -143,14 +139,15 @@ def test_too_few_pairs_takes_no_step():
 
 
 def test_hierarchy_keeps_points_on_the_surface():
-    """Level l back-projects with fx / 2^l and the pixel-centre principal point
-    (cx + 1/2) / 2^l - 1/2: at the pose the depth was taken from, a coarse pixel
-    (mean of its parents) lies on the floor up to the second-order error of
-    averaging depths; a quarter-pixel slip of the principal point would put it
-    millimetres off (the camera is rolled, so both image axes climb the floor)."""
+    """Level l back-projects pixel (u, v) as input pixel (2^l u, 2^l v), i.e. with
+    fx / 2^l and cx / 2^l: at the pose the depth was taken from, every level's
+    points lie on the floor to float32 depth rounding; a half-pixel slip of the
+    principal point would put them millimetres off (the camera is rolled, so
+    both image axes climb the floor).  And each point pairs with the reference
+    pixel it came from."""
     T_ref = synth.pose_look_at([0.3, 1.5, 0.2], [0.5, 0.0, 1.2], [0.5, 1, 0])
     depth, V, N = synth.render_plane_maps(FLOOR, K, W, H, T_ref)
-    for level, bar in ((0, 1e-6), (1, 3e-5), (2, 1.5e-4)):
-        s = oracle.icp_system(depth.astype(np.float32), K, level, V, N, T_ref, T_ref, 0.05)
+    for level in (0, 1, 2, 3):
+        s = oracle.icp_system(depth.astype(np.float32), K, level, V, N, T_ref, T_ref, 1e-5)
         assert s[28] == (W >> level) * (H >> level)
-        assert np.sqrt(s[27] / s[28]) < bar, (level, np.sqrt(s[27] / s[28]))
+        assert np.sqrt(s[27] / s[28]) < 1e-6, (level, np.sqrt(s[27] / s[28]))
