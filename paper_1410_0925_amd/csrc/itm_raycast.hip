@@ -330,7 +330,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             cb.fetch(a.h, s_bfilt, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
         float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
         stencil(cb, sdf, ix, iy, iz, ix == jx && iy == jy && iz == jz, Fc, Ex, Ey, Ez);
-        float gx, gy, gz;
+        float gx = 0.0f, gy = 0.0f, gz = 0.0f;
         gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
         // the hit in metres, (o + t d) s in binary64 from the march's binary32 terms
         P = make_float4((float)(g.s * ((double)ox + (double)t * (double)dx)),

@@ -121,7 +121,11 @@ def compare_raycast(g_ray, o_ray, T_wc, min_cohit=0.995, min_close=0.999):
     close = (dz <= DEPTH_TOL).mean() if both.any() else 1.0
     assert agree >= min_cohit, f"hit/miss agreement {agree:.5f}"
     assert close >= min_close, f"co-hit within 0.5 mm {close:.5f}, p99.9 {np.percentile(dz, 99.9):.2e}"
-    # normals of co-hit pixels with a valid gradient on both sides
+    # normals: valid on the GPU wherever the oracle's are (co-hit pixels), and
+    # within 8 degrees of them
+    ovalid = both & (onrm[..., 3] > 0)
+    if ovalid.any():
+        assert (N[..., 3] > 0)[ovalid].mean() >= min_close, "normals missing on the GPU"
     nb = both & (N[..., 3] > 0) & (onrm[..., 3] > 0)
     cosang = (N[..., :3].astype(np.float64) * onrm[..., :3]).sum(-1)[nb]
     if nb.any():
