@@ -177,12 +177,67 @@ itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
  * enabled are kept until read).  Kernel ids: 0 allocation with the visible
  * list (and, with the search range on, the expected-depth binning), 1
  * integration, 2 raycast (with the binning for a pose other than the last
- * frame's), 3 refiner gate. */
-#define ITM_KERNEL_COUNT 4
+ * frame's), 3 refiner gate, 4 tracker pairing and sums on the finest level,
+ * 5 tracker pairing and sums on the coarser levels, 6 tracker solve and pose
+ * update (every level). */
+#define ITM_KERNEL_COUNT 7
 itm_status itm_profile_enable(itm_scene *scene, int enable);
 /* Synchronises, then writes the summed milliseconds and launch counts per kernel
  * id since profiling was enabled, and resets them. */
 itm_status itm_profile_read(itm_scene *scene, double *ms, int64_t *launches);
+
+/* ------------------------------------------------------------------------ */
+/* Depth tracker, section "Tracking" (the depth tracker): the camera pose of a  */
+/* new depth image is found by aligning it to the surface the raycast rendered  */
+/* from a reference pose.  Each point p of the depth image, moved by the        */
+/* current estimate T (camera -> world), is projected into the reference view   */
+/* with K and paired with the nearest reference pixel (floor(x + 1/2),          */
+/* floor(y + 1/2)); a pair counts when both maps hold a hit there and           */
+/* |T p - V| <= the level's distance threshold.  Its point-to-plane distance is */
+/* d = (T p - V) . N.  A Gauss-Newton step solves A x = -g with A = sum J J^T,  */
+/* g = sum J d, J = (T p x N, N) and moves the pose by T <- (exp([x_0..2]x),    */
+/* x_3..5) T.  Levels of a resolution hierarchy are visited coarse to fine:     */
+/* pixel (u, v) of level l is input pixel (2^l u, 2^l v) (ceil(W / 2^l) x       */
+/* ceil(H / 2^l) pixels), with intrinsics fx / 2^l, fy / 2^l, cx / 2^l,         */
+/* cy / 2^l; the image must have at least 2^l pixels per axis for level l.      */
+/* Per-pixel terms in float32; sums of a workgroup in float32, over             */
+/* workgroups in float64 in a fixed order; the 6 x 6 solve (Cholesky) and the   */
+/* pose (Rodrigues' formula) in float64, on the GPU: no host round trip between */
+/* steps.                                                                       */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t n_levels;       /* 1..4 */
+    int32_t iters[4];       /* Gauss-Newton steps per level, finest first, >= 0 */
+    float dist_thresh[4];   /* pairing distance per level in metres, finest first, > 0 */
+    int32_t min_inliers;    /* a level stops at the first system with fewer pairs */
+} itm_track_params;
+/* n_levels 3, iters {4, 6, 10}, dist_thresh {0.02, 0.05, 0.1}, min_inliers 100 */
+void itm_track_default_params(itm_track_params *params);
+
+typedef struct {
+    int64_t n_pairs;        /* pairs of the last system evaluated */
+    double rms;             /* RMS point-to-plane distance of that system (m) */
+    int32_t steps;          /* Gauss-Newton steps taken over all levels */
+} itm_track_info;
+
+/* depth: DEVICE float32 [K->height][K->width] row-major metres (0, negative,
+ * NaN or inf = invalid); ref_pts, ref_normals: DEVICE float4 [height][width],
+ * 16-byte aligned, as itm_raycast writes them (world frame, w > 0 = hit) for
+ * the same K at pose T_ref; T_ref, T_init: HOST double[16] row-major camera ->
+ * world; params: NULL for the defaults.  T_out: HOST double[16], info: HOST,
+ * may be NULL.  Runs on the scene's stream and synchronises it once at the end
+ * to return the pose.  Scratch (per-workgroup sums, pose) is the scene's,
+ * allocated on first use.  ITM_ERR_ARG for NULL inputs, bad sizes, misaligned
+ * maps or parameters out of range. */
+itm_status itm_track(itm_scene *scene, const float *depth, const itm_intrinsics *K, const float *ref_pts,
+                     const float *ref_normals, const double *T_ref, const double *T_init,
+                     const itm_track_params *params, double *T_out, itm_track_info *info);
+/* The sums of one Gauss-Newton step at pose T on hierarchy level `level` (0 =
+ * the input image): sys HOST double[29] = upper triangle of A row by row (21),
+ * g (6), sum of d^2, number of pairs.  Synchronises.  Arguments as itm_track. */
+itm_status itm_icp_system(itm_scene *scene, const float *depth, const itm_intrinsics *K, int32_t level,
+                          const float *ref_pts, const float *ref_normals, const double *T_ref, const double *T,
+                          float dist_thresh, double *sys);
 
 /* ------------------------------------------------------------------------ */
 /* Learned block refiner.  Not part of the paper's method: a small 3D           */

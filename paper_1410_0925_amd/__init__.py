@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libitm.so")
 ITM_OK, ITM_ERR_ARG, ITM_ERR_OOM, ITM_ERR_HIP, ITM_ERR_STATE = 0, -1, -2, -3, -4
 ITM_VOX_F32, ITM_VOX_F16, ITM_VOX_S16U8 = 0, 1, 2
 FORMATS = {"f32": ITM_VOX_F32, "f16": ITM_VOX_F16, "s16u8": ITM_VOX_S16U8}
-KERNELS = ("alloc", "integrate", "raycast", "refine")
+KERNELS = ("alloc", "integrate", "raycast", "refine", "icp_fine", "icp_coarse", "icp_solve")
 ITM_KERNEL_COUNT = len(KERNELS)
 
 
@@ -32,6 +32,15 @@ class ItmError(RuntimeError):
 class itm_intrinsics(C.Structure):
     _fields_ = [("fx", C.c_double), ("fy", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
                 ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class itm_track_params(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("iters", C.c_int32 * 4), ("dist_thresh", C.c_float * 4),
+                ("min_inliers", C.c_int32)]
+
+
+class itm_track_info(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("rms", C.c_double), ("steps", C.c_int32)]
 
 
 class itm_stats(C.Structure):
@@ -49,7 +58,8 @@ EXPORTED = ("itm_scene_create", "itm_scene_create_ex", "itm_scene_destroy", "itm
             "itm_refiner_create", "itm_refiner_destroy", "itm_refiner_set_stream",
             "itm_refiner_get_params", "itm_refiner_forward", "itm_refiner_gradient",
             "itm_refiner_train_step", "itm_gather_blocks", "itm_scene_set_refiner",
-            "itm_export_blocks_refined", "itm_scene_set_search_range", "itm_expected_depths")
+            "itm_export_blocks_refined", "itm_scene_set_search_range", "itm_expected_depths",
+            "itm_track_default_params", "itm_track", "itm_icp_system")
 ITM_REFINE_PARAMS = 27712
 
 
@@ -86,6 +96,11 @@ def lib():
             "itm_export_blocks_refined": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
             "itm_scene_set_search_range": (C.c_int, [_P, C.c_int32, C.c_int32]),
             "itm_expected_depths": (C.c_int, [_P, C.POINTER(itm_intrinsics), _P, _P]),
+            "itm_track_default_params": (None, [C.POINTER(itm_track_params)]),
+            "itm_track": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), _P, _P, _P, _P,
+                                    C.POINTER(itm_track_params), _P, C.POINTER(itm_track_info)]),
+            "itm_icp_system": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), C.c_int32, _P, _P, _P, _P,
+                                         C.c_float, _P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -180,6 +195,59 @@ def itm_expected_depths(h, K, T_wc, out):
     z = _dev(out, "torch.float32", Ki.width * Ki.height * 2)
     T, Tp = _pose(T_wc)
     _check(lib().itm_expected_depths(h, C.byref(Ki), Tp, z))
+
+
+def itm_track_default_params():
+    p = itm_track_params()
+    lib().itm_track_default_params(C.byref(p))
+    return p
+
+
+def track_params(iters=None, dist=None, min_inliers=None):
+    """itm_track_params from per-level lists (finest first); unset fields keep
+    the library's defaults."""
+    p = itm_track_default_params()
+    if iters is not None:
+        if not 1 <= len(iters) <= 4:
+            raise ValueError("1 to 4 levels")
+        p.n_levels = len(iters)
+        for i, v in enumerate(iters):
+            p.iters[i] = int(v)
+    if dist is not None:
+        for i, v in enumerate(dist):
+            p.dist_thresh[i] = float(v)
+    if min_inliers is not None:
+        p.min_inliers = int(min_inliers)
+    return p
+
+
+def itm_track(h, depth, K, ref_pts, ref_normals, T_ref, T_init, params=None):
+    Ki = _intr(K)
+    n = Ki.width * Ki.height
+    d = _dev(depth, "torch.float32", n)
+    v = _dev(ref_pts, "torch.float32", 4 * n)
+    q = _dev(ref_normals, "torch.float32", 4 * n)
+    Tr, Trp = _pose(T_ref)
+    Ti, Tip = _pose(T_init)
+    out = np.empty(16, np.float64)
+    info = itm_track_info()
+    _check(lib().itm_track(h, d, C.byref(Ki), v, q, Trp, Tip, C.byref(params) if params is not None else None,
+                           out.ctypes.data_as(_P), C.byref(info)))
+    return out.reshape(4, 4), {"pairs": int(info.n_pairs), "rms": float(info.rms), "steps": int(info.steps)}
+
+
+def itm_icp_system(h, depth, K, level, ref_pts, ref_normals, T_ref, T, dist_thresh):
+    Ki = _intr(K)
+    n = Ki.width * Ki.height
+    d = _dev(depth, "torch.float32", n)
+    v = _dev(ref_pts, "torch.float32", 4 * n)
+    q = _dev(ref_normals, "torch.float32", 4 * n)
+    Tr, Trp = _pose(T_ref)
+    T2, Tp = _pose(T)
+    sys_ = np.empty(29, np.float64)
+    _check(lib().itm_icp_system(h, d, C.byref(Ki), int(level), v, q, Trp, Tp, float(dist_thresh),
+                                sys_.ctypes.data_as(_P)))
+    return sys_
 
 
 def itm_export_blocks(h, values=True):
@@ -386,6 +454,22 @@ class Scene:
         self._sync_stream()
         itm_expected_depths(self.h, Ki, T_wc, out)
         return out
+
+    def track(self, depth, K, ref_pts, ref_normals, T_ref, T_init=None, iters=None, dist=None,
+              min_inliers=None):
+        """Pose of `depth` (camera -> world, [4, 4]) by point-to-plane alignment to
+        the reference maps a raycast wrote at T_ref, and {pairs, rms, steps}.
+        iters / dist: per level, finest first (default (4, 6, 10) / (0.02, 0.05,
+        0.1) m)."""
+        self._sync_stream()
+        p = track_params(iters, dist, min_inliers)
+        return itm_track(self.h, depth, K, ref_pts, ref_normals, T_ref, T_ref if T_init is None else T_init, p)
+
+    def icp_system(self, depth, K, level, ref_pts, ref_normals, T_ref, T, dist_thresh):
+        """The 29 sums of one Gauss-Newton step at pose T on hierarchy level
+        `level` (upper triangle of A, g, sum d^2, pairs)."""
+        self._sync_stream()
+        return itm_icp_system(self.h, depth, K, level, ref_pts, ref_normals, T_ref, T, dist_thresh)
 
     def export(self, values=True):
         self._sync_stream()

@@ -99,6 +99,12 @@ struct itm_scene {
     itm_intrinsics fused_K = {};
     double fused_T[16] = {};
 
+    // depth tracker scratch, allocated on first use
+    float *trk_part = nullptr;        // [trk_part_cap][kIcpSums] per-workgroup sums
+    int32_t trk_part_cap = 0;
+    double *trk_pose = nullptr;       // [16] current estimate, then [32] the last system
+    int32_t *trk_flags = nullptr;     // [kTrackLevels] stop flags, then the step count
+
     bool prof = false;
     std::vector<hipEvent_t> ev;     // 2 per slot
     std::vector<int> ev_kernel;
@@ -132,6 +138,9 @@ void release(itm_scene *sc)
     (void)hipFree(sc->occ);
     (void)hipFree(sc->refined);
     (void)hipFree(sc->stamp);
+    (void)hipFree(sc->trk_part);
+    (void)hipFree(sc->trk_pose);
+    (void)hipFree(sc->trk_flags);
     delete sc;
 }
 
@@ -727,6 +736,194 @@ itm_status itm_profile_read(itm_scene *sc, double *ms, int64_t *launches)
     }
     return ITM_OK;
 }
+
+// ---------------------------------------------------------------------------
+// depth tracker
+// ---------------------------------------------------------------------------
+namespace {
+
+// scratch: per-workgroup sums, pose and flags
+itm_status track_scratch(itm_scene *sc)
+{
+    if (!sc->trk_part) {
+        sc->trk_part_cap = 4 * sc->num_cu;
+        if (itm_status st = dev_alloc((void **)&sc->trk_part, sizeof(float) * kIcpSums * (size_t)sc->trk_part_cap,
+                                      "tracker sums"))
+            return st;
+        if (itm_status st = dev_alloc((void **)&sc->trk_pose, sizeof(double) * 48, "tracker pose")) return st;
+        if (itm_status st = dev_alloc((void **)&sc->trk_flags, sizeof(int32_t) * (kTrackLevels + 1), "tracker flags"))
+            return st;
+    }
+    return ITM_OK;
+}
+
+itm_status track_check(const itm_scene *sc, const float *depth, const itm_intrinsics *K, const float *pts,
+                       const float *nrm, const double *T_ref, const double *T)
+{
+    if (!sc || !depth || !K || !pts || !nrm || !T_ref || !T) return fail(ITM_ERR_ARG, "NULL argument");
+    if (K->width < 1 || K->height < 1 || (int64_t)K->width * K->height > (int64_t)1 << 28)
+        return fail(ITM_ERR_ARG, "image size %d x %d out of range", K->width, K->height);
+    if (!(K->fx > 0) || !(K->fy > 0) || !std::isfinite(K->fx) || !std::isfinite(K->fy) || !std::isfinite(K->cx) ||
+        !std::isfinite(K->cy))
+        return fail(ITM_ERR_ARG, "intrinsics must have finite fx, fy > 0 and finite cx, cy");
+    if (((uintptr_t)pts | (uintptr_t)nrm) & 15u) return fail(ITM_ERR_ARG, "reference maps must be 16-byte aligned");
+    for (int i = 0; i < 16; i++)
+        if (!std::isfinite(T_ref[i]) || !std::isfinite(T[i])) return fail(ITM_ERR_ARG, "pose not finite");
+    return ITM_OK;
+}
+
+// level l of the hierarchy: input pixel (2^l u, 2^l v) as pixel (u, v), with
+// intrinsics fx / 2^l, fy / 2^l, cx / 2^l, cy / 2^l
+IcpArgs icp_args(const itm_scene *sc, const float *depth, const itm_intrinsics *K, int level, const float *pts,
+                 const float *nrm, const double *T_ref, float dist)
+{
+    IcpArgs a;
+    a.depth = depth;
+    a.level = level;
+    a.wl = (K->width + (1 << level) - 1) >> level;
+    a.hl = (K->height + (1 << level) - 1) >> level;
+    const double f = std::ldexp(1.0, -level);
+    a.fxl = (float)(K->fx * f);
+    a.fyl = (float)(K->fy * f);
+    a.cxl = (float)(K->cx * f);
+    a.cyl = (float)(K->cy * f);
+    a.fx = (float)K->fx;
+    a.fy = (float)K->fy;
+    a.cx = (float)K->cx;
+    a.cy = (float)K->cy;
+    a.W = K->width;
+    a.H = K->height;
+    a.V = reinterpret_cast<const float4 *>(pts);
+    a.N = reinterpret_cast<const float4 *>(nrm);
+    for (int i = 0; i < 3; i++) {
+        for (int j = 0; j < 3; j++) a.Rr[3 * i + j] = (float)T_ref[4 * i + j];
+        a.tr[i] = (float)T_ref[4 * i + 3];
+    }
+    a.dist = dist;
+    a.pose = sc->trk_pose;
+    a.stop = nullptr;
+    a.part = sc->trk_part;
+    return a;
+}
+
+int icp_grid(const itm_scene *sc, const IcpArgs &a)
+{
+    return (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)a.wl * a.hl + 255) / 256, sc->trk_part_cap));
+}
+
+PoseInit pose_init(itm_scene *sc, const double *T)
+{
+    PoseInit p;
+    std::memcpy(p.T, T, sizeof p.T);
+    p.pose = sc->trk_pose;
+    p.stop = sc->trk_flags;
+    p.steps = sc->trk_flags + kTrackLevels;
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+void itm_track_default_params(itm_track_params *p)
+{
+    if (!p) return;
+    p->n_levels = 3;
+    p->iters[0] = 4; p->iters[1] = 6; p->iters[2] = 10; p->iters[3] = 10;
+    p->dist_thresh[0] = 0.02f; p->dist_thresh[1] = 0.05f; p->dist_thresh[2] = 0.1f; p->dist_thresh[3] = 0.2f;
+    p->min_inliers = 100;
+}
+
+itm_status itm_track(itm_scene *sc, const float *depth, const itm_intrinsics *K, const float *ref_pts,
+                     const float *ref_normals, const double *T_ref, const double *T_init,
+                     const itm_track_params *params, double *T_out, itm_track_info *info)
+{
+    if (itm_status st = track_check(sc, depth, K, ref_pts, ref_normals, T_ref, T_init)) return st;
+    if (!T_out) return fail(ITM_ERR_ARG, "NULL T_out");
+    itm_track_params p;
+    if (params) p = *params;
+    else itm_track_default_params(&p);
+    if (p.n_levels < 1 || p.n_levels > kTrackLevels)
+        return fail(ITM_ERR_ARG, "n_levels %d not in [1, %d]", p.n_levels, kTrackLevels);
+    for (int l = 0; l < p.n_levels; l++) {
+        if (p.iters[l] < 0 || p.iters[l] > 1000) return fail(ITM_ERR_ARG, "iters[%d] = %d not in [0, 1000]", l, p.iters[l]);
+        if (!(p.dist_thresh[l] > 0) || !std::isfinite(p.dist_thresh[l]))
+            return fail(ITM_ERR_ARG, "dist_thresh[%d] must be finite and > 0", l);
+    }
+    for (int l = 1; l < p.n_levels; l++)
+        if ((K->width >> l) < 1 || (K->height >> l) < 1)
+            return fail(ITM_ERR_ARG, "a %d x %d image has no level %d", K->width, K->height, l);
+    if (itm_status st = track_scratch(sc)) return st;
+    HIP_TRY(launch_track_init(pose_init(sc, T_init), sc->stream));
+    for (int l = p.n_levels - 1; l >= 0; l--) {
+        IcpArgs a = icp_args(sc, depth, K, l, ref_pts, ref_normals, T_ref, p.dist_thresh[l]);
+        a.stop = sc->trk_flags + l;
+        SolveArgs s;
+        s.part = sc->trk_part;
+        s.n_part = icp_grid(sc, a);
+        s.pose = sc->trk_pose;
+        s.stop = sc->trk_flags + l;
+        s.steps = sc->trk_flags + kTrackLevels;
+        s.sys = sc->trk_pose + 16;
+        s.min_inliers = p.min_inliers;
+        s.update = 1;
+        for (int it = 0; it < p.iters[l]; it++) {
+            {
+                ProfScope ps(sc, l == 0 ? 4 : 5);
+                HIP_TRY(launch_icp_sums(a, s.n_part, sc->stream));
+            }
+            ProfScope ps(sc, 6);
+            HIP_TRY(launch_icp_solve(s, sc->stream));
+        }
+    }
+    double host[48];
+    int32_t flags[kTrackLevels + 1];
+    HIP_TRY(hipMemcpyAsync(host, sc->trk_pose, sizeof host, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipMemcpyAsync(flags, sc->trk_flags, sizeof flags, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    std::memcpy(T_out, host, sizeof(double) * 16);
+    if (info) {
+        // the last system evaluated (zeros when no step ran)
+        bool any = false;
+        for (int l = 0; l < p.n_levels; l++) any = any || p.iters[l] > 0;
+        const double *sys = host + 16;
+        info->n_pairs = any ? (int64_t)sys[28] : 0;
+        info->rms = any && sys[28] > 0 ? std::sqrt(sys[27] / sys[28]) : 0.0;
+        info->steps = flags[kTrackLevels];
+    }
+    return ITM_OK;
+}
+
+itm_status itm_icp_system(itm_scene *sc, const float *depth, const itm_intrinsics *K, int32_t level,
+                          const float *ref_pts, const float *ref_normals, const double *T_ref, const double *T,
+                          float dist_thresh, double *sys)
+{
+    if (itm_status st = track_check(sc, depth, K, ref_pts, ref_normals, T_ref, T)) return st;
+    if (!sys) return fail(ITM_ERR_ARG, "NULL sys");
+    if (level < 0 || level >= kTrackLevels) return fail(ITM_ERR_ARG, "level %d not in [0, %d)", level, kTrackLevels);
+    if (!(dist_thresh > 0) || !std::isfinite(dist_thresh)) return fail(ITM_ERR_ARG, "dist_thresh must be finite and > 0");
+    if ((K->width >> level) < 1 || (K->height >> level) < 1)
+        return fail(ITM_ERR_ARG, "a %d x %d image has no level %d", K->width, K->height, level);
+    if (itm_status st = track_scratch(sc)) return st;
+    HIP_TRY(launch_track_init(pose_init(sc, T), sc->stream));
+    const IcpArgs a = icp_args(sc, depth, K, level, ref_pts, ref_normals, T_ref, dist_thresh);
+    SolveArgs s;
+    s.part = sc->trk_part;
+    s.n_part = icp_grid(sc, a);
+    s.pose = sc->trk_pose;
+    s.stop = nullptr;
+    s.steps = nullptr;
+    s.sys = sc->trk_pose + 16;
+    s.min_inliers = 0;
+    s.update = 0;
+    HIP_TRY(launch_icp_sums(a, s.n_part, sc->stream));
+    HIP_TRY(launch_icp_solve(s, sc->stream));
+    HIP_TRY(hipMemcpyAsync(sys, sc->trk_pose + 16, sizeof(double) * kIcpSums, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    return ITM_OK;
+}
+
+}  // extern "C"
 
 // ---------------------------------------------------------------------------
 // learned refiner

@@ -1,0 +1,179 @@
+"""Depth tracker (section "Tracking") on the GPU through the C ABI against the
+oracle.
+
+Bars.  The sums of one Gauss-Newton step: pair counts within 0.1% + 20 (a point
+whose projection lies within float32 rounding of a pixel boundary or of the
+distance threshold may pair differently), A within 1e-3 of its diagonal scale
+sqrt(A_ii A_jj), g within 1e-3 of its Cauchy-Schwarz scale sqrt(A_ii sum d^2), the
+sum of d^2 within 1e-3 relative (per-pixel terms are float32 on the GPU, float64
+in the oracle).  A tracked pose: within 1e-4 m and 1e-4 rad of the oracle's from
+the same inputs and iteration counts.
+"""
+import numpy as np
+import pytest
+from scipy.spatial.transform import Rotation
+
+import oracle
+import synth
+from tests.gpu_util import K_of, fuse_gpu, gpu
+
+pytestmark = pytest.mark.gpu
+
+CORNER = [[1, 0, 0, 0], [0, 1, 0, 0], [0, 0, 1, 0]]
+T_REF = synth.pose_look_at([1.5, 1.2, 1.8], [0.2, 0.2, 0.2], [0, 1, 0])
+
+
+def moved(T, w, v):
+    Ri = Rotation.from_rotvec(w).as_matrix()
+    out = np.eye(4)
+    out[:3, :3] = Ri @ T[:3, :3]
+    out[:3, 3] = Ri @ T[:3, 3] + np.asarray(v, np.float64)
+    return out
+
+
+def pose_gap(A, B):
+    ang = np.linalg.norm(Rotation.from_matrix(A[:3, :3] @ B[:3, :3].T).as_rotvec())
+    return ang, np.abs(A[:3, 3] - B[:3, 3]).max()
+
+
+def compare_systems(g, o):
+    assert abs(g[28] - o[28]) <= 20 + 1e-3 * o[28], (g[28], o[28])
+    A_g, A_o = np.zeros((6, 6)), np.zeros((6, 6))
+    k = 0
+    for i in range(6):
+        for j in range(i, 6):
+            A_g[i, j] = A_g[j, i] = g[k]
+            A_o[i, j] = A_o[j, i] = o[k]
+            k += 1
+    d = np.sqrt(np.outer(np.diag(A_o), np.diag(A_o)))
+    assert np.all(np.abs(A_g - A_o) <= 1e-3 * d), np.abs(A_g - A_o).max()
+    gs = np.sqrt(np.diag(A_o) * o[27])
+    assert np.all(np.abs(g[21:27] - o[21:27]) <= 1e-3 * gs + 1e-12), (g[21:27], o[21:27])
+    assert abs(g[27] - o[27]) <= 1e-3 * o[27] + 1e-12
+
+
+def corner_case(K, W, H, T_true):
+    _, V, N = synth.render_plane_maps(CORNER, K, W, H, T_REF)
+    depth = synth.render_plane_maps(CORNER, K, W, H, T_true)[0].astype(np.float32)
+    return depth, V, N
+
+
+def upload(torch, *arrays):
+    return [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in arrays]
+
+
+@pytest.mark.parametrize("size", [(160, 120), (97, 61)])
+def test_sums_match_the_oracle(size):
+    itm, torch = gpu()
+    W, H = size
+    K = (140.0 * W / 160, 140.0 * W / 160, (W - 1) / 2, (H - 1) / 2)
+    T_true = moved(T_REF, [0.02, -0.03, 0.01], [0.03, -0.02, 0.025])
+    depth, V, N = corner_case(K, W, H, T_true)
+    depth[::7, ::5] = 0.0          # holes
+    depth[3, :] = np.nan
+    d_g, V_g, N_g = upload(torch, depth, V, N)
+    sc = itm.Scene(0.01, 0.04, 100, 1 << 12, 1 << 10)
+    for level in (0, 1, 2):
+        for T in (T_REF, T_true, moved(T_true, [0.003, 0, -0.002], [0.004, 0.002, 0])):
+            print(f"case: corner {W}x{H}, level {level}", flush=True)
+            g = sc.icp_system(d_g, K + (W, H), level, V_g, N_g, T_REF, T, 0.05)
+            o = oracle.icp_system(depth, K, level, V, N, T_REF, T, 0.05)
+            assert o[28] > 50
+            compare_systems(g, o)
+
+
+def test_tracks_a_known_motion_like_the_oracle():
+    itm, torch = gpu()
+    W, H, K = 160, 120, (140.0, 140.0, 79.5, 59.5)
+    T_true = moved(T_REF, [0.02, -0.03, 0.01], [0.03, -0.02, 0.025])
+    depth, V, N = corner_case(K, W, H, T_true)
+    d_g, V_g, N_g = upload(torch, depth, V, N)
+    sc = itm.Scene(0.01, 0.04, 100, 1 << 12, 1 << 10)
+    print("case: corner 160x120 track", flush=True)
+    T_g, info_g = sc.track(d_g, K + (W, H), V_g, N_g, T_REF, iters=(6, 6, 6), dist=(0.05, 0.1, 0.2))
+    T_o, info_o = oracle.track(depth, K, V, N, T_REF, T_REF, iters=(6, 6, 6), dist=(0.05, 0.1, 0.2))
+    assert info_g["steps"] == info_o["steps"] == 18
+    ang, tr = pose_gap(T_g, T_o)
+    assert ang < 1e-4 and tr < 1e-4, (ang, tr)
+    ang, tr = pose_gap(T_g, T_true)
+    assert ang < 1e-4 and tr < 1e-4, (ang, tr)
+    assert abs(info_g["pairs"] - info_o["pairs"]) <= 20 + 1e-3 * info_o["pairs"]
+    assert abs(np.linalg.det(T_g[:3, :3]) - 1) < 1e-9 and np.array_equal(T_g[3], [0, 0, 0, 1])
+
+
+def test_tracks_a_fused_scene_like_the_oracle():
+    """Reference maps from the GPU raycast of the first 20 frames of the VGA
+    stream at frame 19's pose; the depth of frame 21 is tracked from there."""
+    itm, torch = gpu()
+    st = synth.make_stream("vga", n_frames=22)
+    print("case: vga 20 frames fused, track frame 21 from frame 19", flush=True)
+    sc, rays, _ = fuse_gpu(st, frames=20, ray_frames=(19,))
+    V, N = rays[19]
+    K = K_of(st)
+    d_g, V_g, N_g = upload(torch, st.depth[21], V, N)
+    T_ref = st.T_wc[19]
+    T_g, info_g = sc.track(d_g, K, V_g, N_g, T_ref)
+    T_o, info_o = oracle.track(st.depth[21], st.intrinsics, V, N, T_ref, T_ref)
+    assert info_g["steps"] == info_o["steps"] and info_g["steps"] > 0
+    ang, tr = pose_gap(T_g, T_o)
+    assert ang < 1e-4 and tr < 1e-4, (ang, tr)
+    # and it finds the motion: far closer to frame 21's pose than the start was
+    ang0, tr0 = pose_gap(T_ref, st.T_wc[21])
+    ang1, tr1 = pose_gap(T_g, st.T_wc[21])
+    print(f"start {ang0:.2e} rad {tr0:.2e} m -> tracked {ang1:.2e} rad {tr1:.2e} m, rms {info_g['rms']:.2e}")
+    assert tr1 < 0.2 * tr0 and ang1 < 0.2 * ang0 + 1e-4
+    # one full-size system at the start pose, as the first fine step sees it
+    g = sc.icp_system(d_g, K, 0, V_g, N_g, T_ref, T_ref, 0.02)
+    o = oracle.icp_system(st.depth[21], st.intrinsics, 0, V, N, T_ref, T_ref, 0.02)
+    compare_systems(g, o)
+
+
+def test_degenerate_inputs():
+    itm, torch = gpu()
+    W, H, K = 160, 120, (140.0, 140.0, 79.5, 59.5)
+    T_true = moved(T_REF, [0.0, 0.01, 0.0], [0.01, 0.0, 0.0])
+    depth, V, N = corner_case(K, W, H, T_true)
+    d_g, V_g, N_g = upload(torch, depth, V, N)
+    sc = itm.Scene(0.01, 0.04, 100, 1 << 12, 1 << 10)
+    KK = K + (W, H)
+    print("case: tracker degenerate inputs", flush=True)
+    # no reference surface: no pairs, no step, pose unchanged
+    Z = torch.zeros_like(V_g)
+    T, info = sc.track(d_g, KK, Z, Z, T_REF)
+    assert info["steps"] == 0 and info["pairs"] == 0
+    np.testing.assert_array_equal(T, T_REF)
+    # no valid depth
+    T, info = sc.track(torch.zeros_like(d_g), KK, V_g, N_g, T_REF)
+    assert info["steps"] == 0 and info["pairs"] == 0
+    # too few pairs for the threshold
+    T, info = sc.track(d_g, KK, V_g, N_g, T_REF, min_inliers=10 ** 9)
+    assert info["steps"] == 0 and info["pairs"] > 0
+    np.testing.assert_array_equal(T, T_REF)
+    # zero iterations: the initial pose comes back
+    T_init = moved(T_REF, [0.001, 0, 0], [0, 0, 0.002])
+    T, info = sc.track(d_g, KK, V_g, N_g, T_REF, T_init=T_init, iters=(0, 0))
+    assert info["steps"] == 0
+    np.testing.assert_array_equal(T, T_init)
+    # one level only
+    T1, info1 = sc.track(d_g, KK, V_g, N_g, T_REF, iters=(8,), dist=(0.1,))
+    T1o, info1o = oracle.track(depth, K, V, N, T_REF, T_REF, iters=(8,), dist=(0.1,))
+    ang, tr = pose_gap(T1, T1o)
+    assert info1["steps"] == info1o["steps"] and ang < 1e-4 and tr < 1e-4
+    # errors
+    with pytest.raises(ValueError):
+        sc.track(d_g, KK, V_g, N_g, T_REF, iters=[1] * 5)
+    p5 = itm.track_params()
+    p5.n_levels = 5
+    with pytest.raises(itm.ItmError):
+        itm.itm_track(sc.h, d_g, KK, V_g, N_g, T_REF, T_REF, p5)
+    with pytest.raises(itm.ItmError):
+        sc.track(d_g, KK, V_g, N_g, T_REF, dist=(0.0, 0.05, 0.1))
+    with pytest.raises(itm.ItmError):   # 3 x 2 has no level 2
+        sc.track(d_g.view(-1)[:6], (140.0, 140.0, 1.0, 0.5, 3, 2), V_g.view(-1)[:24], N_g.view(-1)[:24],
+                 T_REF, iters=(1, 1, 1))
+    bad = T_REF.copy()
+    bad[0, 3] = np.nan
+    with pytest.raises(itm.ItmError):
+        sc.icp_system(d_g, KK, 0, V_g, N_g, T_REF, bad, 0.05)
+    with pytest.raises(itm.ItmError):
+        sc.icp_system(d_g, KK, 4, V_g, N_g, T_REF, T_REF, 0.05)
