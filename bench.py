@@ -131,6 +131,56 @@ def learned_leg(itm, torch, steps=20, batch=256):
             "flop_model": "algorithmic: real channels only (layer 1: 2 in, layer 4: 1 out)"}
 
 
+def track_leg(itm, torch, sc, st, depth, K, f, calls, cpu):
+    """Depth tracker (section "Tracking"): frame f's depth aligned to the raycast
+    at frame f - 1's pose, from that pose, with the default hierarchy (levels of
+    640x480, 320x240, 160x120; 4 + 6 + 10 Gauss-Newton steps).  Each call ends
+    with one host synchronisation (the pose is returned to the host)."""
+    W, H = K[4], K[5]
+    V = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    N = torch.empty_like(V)
+    T_ref = st.T_wc[f - 1]
+    sc.raycast(K, T_ref, V, N)
+    for _ in range(2):
+        T, info = sc.track(depth[f], K, V, N, T_ref)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        T, info = sc.track(depth[f], K, V, N, T_ref)
+    wall = time.perf_counter() - t0
+    # per-kernel times from separate calls with HIP events around every launch
+    sc.profile_read()
+    sc.profile(True)
+    for _ in range(5):
+        sc.track(depth[f], K, V, N, T_ref)
+    sc.profile(False)
+    prof = sc.profile_read()
+    ms_f, n_f = prof["icp_fine"]
+    # algorithmic bytes of a finest-level launch: every depth pixel, the two
+    # reference maps at each pair, the workgroup sums
+    b = 4.0 * W * H + 32.0 * info["pairs"] + 4.0 * 29 * min((W * H + 255) // 256, 4 * 256)
+    avg = ms_f / max(n_f, 1)
+    gbs = b / (avg * 1e-3) / 1e9
+    err_t = float(np.abs(T[:3, 3] - st.T_wc[f][:3, 3]).max())
+    out = {"frame": f, "ms_per_call": wall * 1e3 / calls, "calls": calls, "steps_per_call": info["steps"],
+           "pairs_last": info["pairs"], "rms_last_m": info["rms"],
+           "translation_error_m": err_t, "start_translation_error_m": float(np.abs(T_ref[:3, 3] - st.T_wc[f][:3, 3]).max()),
+           "kernels_us": {k: round(prof[k][0] / max(prof[k][1], 1) * 1e3, 3) for k in ("icp_fine", "icp_coarse", "icp_solve")},
+           "icp_fine": {"bytes_per_launch": round(b), "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                        "bound": "hbm"}}
+    if cpu:
+        import oracle
+        d = st.depth[f]
+        Vh, Nh = V.cpu().numpy(), N.cpu().numpy()
+        t0 = time.perf_counter()
+        T_o, _ = oracle.track(d, st.intrinsics, Vh, Nh, T_ref, T_ref)
+        out["cpu_oracle_ms_per_call"] = (time.perf_counter() - t0) * 1e3
+        out["cpu_oracle_cores"] = 1
+        out["oracle_translation_error_m"] = float(np.abs(T_o[:3, 3] - st.T_wc[f][:3, 3]).max())
+        out["gpu_vs_oracle_translation_m"] = float(np.abs(T_o[:3, 3] - T[:3, 3]).max())
+    return out
+
+
 def cpu_baseline(stream, seconds, search_range):
     """The CPU oracle (allocation + integration, plain loops) on the first frames
     of the same stream until about `seconds` of work, then one raycast."""
@@ -175,6 +225,7 @@ def main():
                     help="record per-kernel HIP events on every n-th timed frame")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the refiner timing leg")
+    ap.add_argument("--no-track", action="store_true", help="skip the depth tracker timing leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, copy a buffer of this size once "
@@ -292,6 +343,10 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    if not args.no_track:
+        log("depth tracker: last frame against the raycast at the frame before")
+        out["track"] = track_leg(itm, torch, sc, st, depth, K, args.warmup + args.steps - 1, 20,
+                                 not args.no_cpu_baseline)
     if not args.no_learned:
         log("learned form: refiner training steps and forward passes")
         out["learned"] = learned_leg(itm, torch)

@@ -746,7 +746,9 @@ namespace {
 itm_status track_scratch(itm_scene *sc)
 {
     if (!sc->trk_part) {
-        sc->trk_part_cap = 4 * sc->num_cu;
+        // one workgroup per CU: each thread takes several pixels of the finest
+        // level, so the per-thread reduction of the 29 sums is amortised
+        sc->trk_part_cap = sc->num_cu;
         if (itm_status st = dev_alloc((void **)&sc->trk_part, sizeof(float) * kIcpSums * (size_t)sc->trk_part_cap,
                                       "tracker sums"))
             return st;

@@ -156,26 +156,22 @@ __device__ void pose_step(const double *xi, double *T)
     }
 }
 
-// 29 x 8 threads: thread (k, l) sums partials l, l + 8, ... of component k, then
-// the 8 are added in order -- the same order every call
-__global__ __launch_bounds__(256) void k_icp_solve(SolveArgs a)
+// 32 threads per component: thread (k, l) sums partials l, l + 32, ... of
+// component k, then the wave adds its 32 in a fixed butterfly -- the same order
+// every call
+__global__ __launch_bounds__(1024) void k_icp_solve(SolveArgs a)
 {
     if (a.stop && *a.stop) return;   // the level has stopped: its last system stays
-    __shared__ double s_p[kIcpSums][8];
     __shared__ double s_sys[kIcpSums];
-    const int k = threadIdx.x >> 3, l = threadIdx.x & 7;
-    if (k < kIcpSums) {
-        double acc = 0.0;
-        for (int j = l; j < a.n_part; j += 8) acc += (double)a.part[(int64_t)j * kIcpSums + k];
-        s_p[k][l] = acc;
-    }
-    __syncthreads();
-    if (threadIdx.x < kIcpSums) {
-        const int c = threadIdx.x;
-        double s = 0.0;
-        for (int m = 0; m < 8; m++) s += s_p[c][m];
-        s_sys[c] = s;
-        a.sys[c] = s;
+    const int k = threadIdx.x >> 5, l = threadIdx.x & 31;
+    double acc = 0.0;
+    if (k < kIcpSums)
+        for (int j = l; j < a.n_part; j += 32) acc += (double)a.part[(int64_t)j * kIcpSums + k];
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 32);
+    if (k < kIcpSums && l == 0) {
+        s_sys[k] = acc;
+        a.sys[k] = acc;
     }
     __syncthreads();
     if (threadIdx.x != 0 || !a.update) return;
@@ -206,7 +202,7 @@ hipError_t launch_icp_sums(const IcpArgs &a, int grid, hipStream_t st)
 
 hipError_t launch_icp_solve(const SolveArgs &a, hipStream_t st)
 {
-    k_icp_solve<<<1, 256, 0, st>>>(a);
+    k_icp_solve<<<1, 1024, 0, st>>>(a);
     return hipGetLastError();
 }
 
