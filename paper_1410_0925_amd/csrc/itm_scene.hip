@@ -10,7 +10,7 @@
 #include <string>
 #include <vector>
 
-#include "itm_internal.hpp"
+#include "itm_track.hpp"
 
 using namespace itm;
 

@@ -16,7 +16,7 @@
 // The current pose lives in device memory (float64, row-major 4 x 4); a level
 // that runs out of pairs sets its stop flag, after which the level's remaining
 // launches return at once.
-#include "itm_internal.hpp"
+#include "itm_track.hpp"
 
 namespace itm {
 
