@@ -177,3 +177,36 @@ def test_degenerate_inputs():
         sc.icp_system(d_g, KK, 0, V_g, N_g, T_REF, bad, 0.05)
     with pytest.raises(itm.ItmError):
         sc.icp_system(d_g, KK, 4, V_g, N_g, T_REF, T_REF, 0.05)
+
+
+def test_closed_loop_tracking_and_fusion():
+    """The method's frame loop: each frame is tracked against the raycast at the
+    previous frame's estimated pose, then integrated at its tracked pose.  The map
+    is first built from frames 0..259 at their given poses; frames 260..299 (a
+    stretch whose views hold surfaces facing all three axes: earlier stretches look
+    at walls only, where point-to-plane alignment cannot fix the vertical
+    translation) are then tracked and fused.  The estimated trajectory stays on
+    the true one."""
+    itm, torch = gpu()
+    st = synth.make_stream("vga")
+    print("case: vga closed loop, frames 260..299 tracked", flush=True)
+    sc = itm.Scene.from_params(st.params)
+    sc.set_search_range(True)
+    K = K_of(st)
+    depth = torch.from_numpy(np.ascontiguousarray(st.depth)).cuda()
+    V = torch.empty((st.height, st.width, 4), dtype=torch.float32, device="cuda")
+    N = torch.empty_like(V)
+    for f in range(260):
+        sc.integrate(depth[f], K, st.T_wc[f])
+    T_prev = st.T_wc[259]
+    worst_t = worst_r = 0.0
+    for f in range(260, st.n_frames):
+        sc.raycast(K, T_prev, V, N)
+        T, info = sc.track(depth[f], K, V, N, T_prev)
+        assert info["steps"] > 0 and info["pairs"] > 50000, (f, info)
+        sc.integrate(depth[f], K, T)
+        ang, tr = pose_gap(T, st.T_wc[f])
+        worst_t, worst_r = max(worst_t, tr), max(worst_r, ang)
+        T_prev = T
+    print(f"closed loop: worst translation error {worst_t * 1e3:.2f} mm, rotation {np.degrees(worst_r):.3f} deg")
+    assert worst_t < 0.01 and worst_r < np.radians(0.5)
