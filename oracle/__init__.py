@@ -71,6 +71,10 @@ def lib():
             "orc_raycast_crossing": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
             "orc_expected_depths": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
             "orc_num_threads": (C.c_int, []),
+            "orc_enable_colour": (C.c_int, [_P]),
+            "orc_integrate_colour": (_i64, [_P, _P, _P, C.c_int, C.c_int, _P, _P]),
+            "orc_export_colour": (_i64, [_P, _P, _i64]),
+            "orc_colour_at": (C.c_int, [_P, _P, _i64, _P]),
             "orc_depth_level": (C.c_int, [_P, C.c_int, C.c_int, C.c_int, _P, _P, _P]),
             "orc_icp_system": (C.c_int, [_P, C.c_int, C.c_int, _P, C.c_int, _P, _P, _P, _P, C.c_double, _P]),
             "orc_solve6": (C.c_int, [_P, _P, _P]),
@@ -184,6 +188,41 @@ class Scene:
         Wt = np.empty((n, 512), np.int32) if with_values else None
         lib().orc_export(self.h, _ptr(coords), _ptr(F), _ptr(Wt), n)
         return coords, F, Wt
+
+    def enable_colour(self):
+        """Colour (r, g, b, colour weight) per voxel from now on."""
+        if lib().orc_enable_colour(self.h):
+            raise MemoryError
+
+    def integrate_colour(self, depth, rgbx, intr, T_wc) -> int:
+        """A frame with its registered colour image (uint8 [H, W, 4])."""
+        d = np.ascontiguousarray(depth, np.float32)
+        H, W = d.shape
+        c = np.ascontiguousarray(rgbx, np.uint8)
+        assert c.shape == (H, W, 4)
+        r = int(lib().orc_integrate_colour(self.h, _ptr(d), _ptr(c), W, H, _ptr(_K(intr)),
+                                           _ptr(np.ascontiguousarray(T_wc, np.float64))))
+        if r < 0:
+            raise RuntimeError("colour not enabled or allocation failed")
+        return r
+
+    def export_colour(self):
+        """uint8 [n, 512, 4] (r, g, b, colour weight) in the order of export()."""
+        n = lib().orc_export_colour(self.h, None, 0)
+        if n < 0:
+            raise RuntimeError("colour not enabled")
+        out = np.empty((n, 512, 4), np.uint8)
+        lib().orc_export_colour(self.h, _ptr(out), n)
+        return out
+
+    def colour_at(self, pts):
+        """Colour of the nearest voxel of each hit point (float32 [..., 4], world
+        metres, w > 0 = hit): uint8 [..., 4] = (r, g, b, 255), zeros elsewhere."""
+        p = np.ascontiguousarray(pts, np.float32)
+        out = np.empty(p.shape[:-1] + (4,), np.uint8)
+        if lib().orc_colour_at(self.h, _ptr(p), p.size // 4, _ptr(out)):
+            raise RuntimeError("colour not enabled")
+        return out
 
     def update_voxels(self, depth, intr, T_wc, vox, active, F, Wt) -> int:
         """Apply one frame's update to individual voxels (absolute voxel coords)."""

@@ -30,6 +30,9 @@
  *                                          CreateExpectedDepths)
  *   depth tracker (point-to-plane ICP over
  *     a resolution hierarchy) ............ section "Tracking" (ITMDepthTracker)
+ *   colour voxels (RGB and a colour weight
+ *     per voxel, fused with the depth) ... section "Framework Flexibility"
+ *                                          (ITMVoxel_s_rgb) and "Integration" 
  * Readings where the paper is silent are noted beside the code that takes them.
  */
 #include <math.h>
@@ -66,6 +69,7 @@ typedef struct {
     /* voxel block array, grown on demand; F in [-1,1] (binary64), W integer */
     double *F;
     int32_t *W;
+    uint8_t *C;        /* colour (r, g, b, colour weight) per voxel, NULL until enabled */
     int64_t n_blocks, cap_blocks;
     /* per-frame visibility (one flag per hash entry) and statistics */
     uint8_t *vis;
@@ -122,7 +126,7 @@ orc_scene *orc_scene_create(float voxel_size, float mu, int32_t max_w, int64_t n
 void orc_scene_destroy(orc_scene *sc)
 {
     if (!sc) return;
-    free(sc->e); free(sc->vis); free(sc->F); free(sc->W); free(sc->drop_keys); free(sc);
+    free(sc->e); free(sc->vis); free(sc->F); free(sc->W); free(sc->C); free(sc->drop_keys); free(sc);
 }
 
 int orc_set_range(orc_scene *sc, float z_near, float z_far)
@@ -168,6 +172,11 @@ static int32_t orc_reserve_block(orc_scene *sc)
         int32_t *W = (int32_t *)realloc(sc->W, sizeof(int32_t) * SDF_BLOCK3 * (size_t)nc);
         if (!W) return -2;
         sc->W = W;
+        if (sc->C) {
+            uint8_t *C = (uint8_t *)realloc(sc->C, 4 * SDF_BLOCK3 * (size_t)nc);
+            if (!C) return -2;
+            sc->C = C;
+        }
         sc->cap_blocks = nc;
     }
     int64_t b = sc->n_blocks++;
@@ -175,6 +184,7 @@ static int32_t orc_reserve_block(orc_scene *sc)
         sc->F[b * SDF_BLOCK3 + i] = 1.0;
         sc->W[b * SDF_BLOCK3 + i] = 0;
     }
+    if (sc->C) memset(sc->C + 4 * b * SDF_BLOCK3, 0, 4 * SDF_BLOCK3);
     return (int32_t)b;
 }
 
@@ -423,6 +433,7 @@ typedef struct {
     float fx, fy, cx, cy;  /* binary32 intrinsics for the projection decision */
     float g[3][3];         /* g[j][a]: step along world axis j, camera component a */
     const float *depth;
+    const uint8_t *rgbx;   /* registered colour image, 4 bytes per pixel, or NULL */
     float mu_f;
     double mu, s;
     int max_w;
@@ -436,6 +447,7 @@ static void orc_frame_setup(orc_frame *fr, const orc_scene *sc, const float *dep
     for (int j = 0; j < 3; j++)
         for (int a = 0; a < 3; a++) fr->g[j][a] = (float)(fr->c.Rcw[3 * a + j] * sc->s);
     fr->depth = depth;
+    fr->rgbx = NULL;
     fr->mu_f = sc->mu_f;
     fr->mu = sc->mu;
     fr->s = sc->s;
@@ -459,9 +471,25 @@ static void orc_block_origin(const orc_frame *fr, int32_t kx, int32_t ky, int32_
 }
 
 /* returns 1 when the voxel was updated */
+/* Colour (readings; the paper shows the voxel type and says a similar function
+ * updates the colour): the colour image is registered with the depth image and
+ * read at the same pixel; a voxel whose depth update ran takes a colour sample
+ * when it lies inside the band, eta32 <= mu (binary32, like the other decisions);
+ * each channel keeps the running average of its samples rounded to the nearest
+ * integer (ties to even), new = round((w_c c + sample) / (w_c + 1)) in exact
+ * integer arithmetic, and w_c <- min(w_c + 1, min(max_w, 255)). */
+static uint8_t orc_colour_mean(int c, int w, int sample)
+{
+    const int num = w * c + sample, den = w + 1;
+    int q = num / den;
+    const int r2 = 2 * (num - q * den);
+    if (r2 > den || (r2 == den && (q & 1))) q++;
+    return (uint8_t)q;
+}
+
 static int orc_update_voxel(const orc_frame *fr, const orc_blockorigin *bo, int32_t kx,
                             int32_t ky, int32_t kz, int lx, int ly, int lz, double *F,
-                            int32_t *Wt)
+                            int32_t *Wt, uint8_t *C)
 {
     float fl[3] = {(float)lx, (float)ly, (float)lz};
     float dl[3], p[3];
@@ -476,10 +504,17 @@ static int orc_update_voxel(const orc_frame *fr, const orc_blockorigin *bo, int3
     float x = fr->fx * p[0] / p[2] + fr->cx;
     float y = fr->fy * p[1] / p[2] + fr->cy;
     if (x < 1.0f || x > (float)(fr->c.W - 2) || y < 1.0f || y > (float)(fr->c.H - 2)) return 0;
-    float d = fr->depth[(int)(x + 0.5f) + (int)(y + 0.5f) * fr->c.W];
+    const int pix = (int)(x + 0.5f) + (int)(y + 0.5f) * fr->c.W;
+    float d = fr->depth[pix];
     if (!(d > 0.0f) || isinf(d)) return 0;
     float eta32 = (d - bo->hi[2]) - (bo->lo[2] + dl[2]);
     if (eta32 < -fr->mu_f) return 0;
+    if (C && fr->rgbx && eta32 <= fr->mu_f) {
+        const int wc = C[3];
+        for (int ch = 0; ch < 3; ch++) C[ch] = orc_colour_mean(C[ch], wc, fr->rgbx[4 * pix + ch]);
+        const int cap = fr->max_w < 255 ? fr->max_w : 255;
+        C[3] = (uint8_t)(wc + 1 < cap ? wc + 1 : cap);
+    }
 
     double vs[3] = {(double)(8 * kx + lx) * fr->s, (double)(8 * ky + ly) * fr->s,
                     (double)(8 * kz + lz) * fr->s};
@@ -510,11 +545,13 @@ static int64_t orc_integrate_visible(orc_scene *sc, const orc_frame *fr)
         orc_block_origin(fr, h->x, h->y, h->z, &bo);
         double *F = sc->F + (int64_t)h->ptr * SDF_BLOCK3;
         int32_t *W = sc->W + (int64_t)h->ptr * SDF_BLOCK3;
+        uint8_t *Cb = sc->C ? sc->C + 4 * (int64_t)h->ptr * SDF_BLOCK3 : NULL;
         for (int lz = 0; lz < 8; lz++)
             for (int ly = 0; ly < 8; ly++)
                 for (int lx = 0; lx < 8; lx++) {
                     int li = lx + 8 * ly + 64 * lz;
-                    updated += orc_update_voxel(fr, &bo, h->x, h->y, h->z, lx, ly, lz, &F[li], &W[li]);
+                    updated += orc_update_voxel(fr, &bo, h->x, h->y, h->z, lx, ly, lz, &F[li], &W[li],
+                                                Cb ? Cb + 4 * li : NULL);
                 }
     }
     free(list);
@@ -529,6 +566,27 @@ int64_t orc_integrate(orc_scene *sc, const float *depth, int W, int H, const dou
     if (orc_allocate(sc, depth, W, H, K, T_wc) < 0) return -1;
     orc_frame fr;
     orc_frame_setup(&fr, sc, depth, W, H, K, T_wc);
+    return orc_integrate_visible(sc, &fr);
+}
+
+/* colour voxels: storage for every block, present and future (colour (0, 0, 0),
+   weight 0) */
+int orc_enable_colour(orc_scene *sc)
+{
+    if (sc->C) return 0;
+    sc->C = (uint8_t *)calloc(4 * SDF_BLOCK3 * (size_t)(sc->cap_blocks ? sc->cap_blocks : 1), 1);
+    return sc->C ? 0 : -1;
+}
+
+/* a frame with its registered colour image (4 bytes per pixel: r, g, b, unused) */
+int64_t orc_integrate_colour(orc_scene *sc, const float *depth, const uint8_t *rgbx, int W, int H,
+                             const double *K, const double *T_wc)
+{
+    if (!sc->C) return -1;
+    if (orc_allocate(sc, depth, W, H, K, T_wc) < 0) return -1;
+    orc_frame fr;
+    orc_frame_setup(&fr, sc, depth, W, H, K, T_wc);
+    fr.rgbx = rgbx;
     return orc_integrate_visible(sc, &fr);
 }
 
@@ -614,6 +672,55 @@ int64_t orc_export(const orc_scene *sc, int32_t *coords, double *F, int32_t *Wt,
     return k;
 }
 
+/* colours of the allocated blocks, in the order of orc_export */
+int64_t orc_export_colour(const orc_scene *sc, uint8_t *rgbw, int64_t cap)
+{
+    int64_t n = sc->n_blocks;
+    if (!sc->C) return -1;
+    if (!rgbw || cap < n) return n;
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)(n + 1));
+    if (!tmp) return -1;
+    int64_t k = 0;
+    for (int64_t i = 0; i < sc->n_entries; i++) {
+        if (sc->e[i].ptr < 0) continue;
+        tmp[4 * k] = sc->e[i].x; tmp[4 * k + 1] = sc->e[i].y; tmp[4 * k + 2] = sc->e[i].z;
+        tmp[4 * k + 3] = sc->e[i].ptr;
+        k++;
+    }
+    qsort(tmp, (size_t)k, sizeof(int32_t) * 4, orc_key_cmp);
+    for (int64_t i = 0; i < k; i++)
+        memcpy(rgbw + 4 * i * SDF_BLOCK3, sc->C + 4 * (int64_t)tmp[4 * i + 3] * SDF_BLOCK3, 4 * SDF_BLOCK3);
+    free(tmp);
+    return k;
+}
+
+/* colour at surface points (the raycast's colour read; reading: the colour of
+   the nearest lattice voxel floor(p / s + 1/2), as the march's own reads):
+   (r, g, b, 255) when that voxel's block is allocated, zeros otherwise or where
+   the point is not a hit (w <= 0) */
+int orc_colour_at(const orc_scene *sc, const float *pts, int64_t n, uint8_t *out)
+{
+    if (!sc->C) return -1;
+    for (int64_t i = 0; i < n; i++) {
+        uint8_t *o = out + 4 * i;
+        o[0] = o[1] = o[2] = o[3] = 0;
+        if (!(pts[4 * i + 3] > 0.0f)) continue;
+        int32_t v[3], k[3], l[3];
+        for (int a = 0; a < 3; a++) {
+            v[a] = (int32_t)floor((double)pts[4 * i + a] / sc->s + 0.5);
+            k[a] = v[a] >= 0 ? v[a] / SDF_BLOCK : -((-v[a] + SDF_BLOCK - 1) / SDF_BLOCK);
+            l[a] = v[a] - SDF_BLOCK * k[a];
+        }
+        if (k[0] < -32768 || k[0] > 32767 || k[1] < -32768 || k[1] > 32767 || k[2] < -32768 || k[2] > 32767)
+            continue;
+        const int64_t e = orc_find(sc, k[0], k[1], k[2]);
+        if (e < 0) continue;
+        const uint8_t *c = sc->C + 4 * ((int64_t)sc->e[e].ptr * SDF_BLOCK3 + l[0] + 8 * l[1] + 64 * l[2]);
+        o[0] = c[0]; o[1] = c[1]; o[2] = c[2]; o[3] = 255;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------- */
 /* sampled voxels: the same update applied to a list of individual voxels,     */
 /* for checks of full-size runs voxel by voxel.  active[i] != 0 when voxel i's  */
@@ -636,7 +743,7 @@ int64_t orc_update_voxels(const orc_scene *sc, const float *depth, int W, int H,
         }
         orc_blockorigin bo;
         orc_block_origin(&fr, k[0], k[1], k[2], &bo);
-        upd += orc_update_voxel(&fr, &bo, k[0], k[1], k[2], l[0], l[1], l[2], &F[i], &Wt[i]);
+        upd += orc_update_voxel(&fr, &bo, k[0], k[1], k[2], l[0], l[1], l[2], &F[i], &Wt[i], NULL);
     }
     return upd;
 }
@@ -734,7 +841,7 @@ int64_t orc_dense_integrate(orc_dense *dv, const float *depth, int W, int H, con
                 orc_blockorigin bo;
                 orc_block_origin(&fr, k[0], k[1], k[2], &bo);
                 int64_t i = ix + dv->n[0] * (iy + dv->n[1] * iz);
-                int u = orc_update_voxel(&fr, &bo, k[0], k[1], k[2], l[0], l[1], l[2], &dv->F[i], &dv->W[i]);
+                int u = orc_update_voxel(&fr, &bo, k[0], k[1], k[2], l[0], l[1], l[2], &dv->F[i], &dv->W[i], NULL);
                 if (u && fbit < 64) dv->frames[i] |= (uint64_t)1 << fbit;
                 updated += u;
             }

@@ -7,5 +7,5 @@ per pixel, then sensor noise, dropouts and range truncation are applied. The
 recordings the paper runs on (a Kinect "Teddy" sequence, section "Compilation,
 UI, Usage and Examples") are not available; these streams stand in for them.
 """
-from .scenes import (Scene, Stream, make_stream, render_depth, render_plane_maps, pose_look_at,  # noqa: F401
+from .scenes import (Scene, Stream, make_stream, render_depth, render_plane_maps, pose_look_at, colour_frames,  # noqa: F401
                      WORKLOADS, workload_params)

@@ -402,6 +402,36 @@ def _path_poses(path, rng, n, step=0.06, dang=np.deg2rad(1.0)):
 _STREAM_CACHE: dict = {}
 
 
+# the colour of a surface point: three smooth waves in world space, one per
+# channel (wavelengths 0.3-0.5 m), mid grey +- 110
+_CLR_DIR = np.array([[2.3, 0.7, -1.1], [-0.9, 2.8, 0.6], [1.2, -1.4, 2.5]])
+_CLR_PHASE = np.array([0.3, 1.9, 4.1])
+
+
+def colour_frames(stream: Stream, frames=None, seed: int = 17) -> np.ndarray:
+    """Registered colour images (same camera as the depth): uint8 [n, H, W, 4]
+    (R, G, B, 0), the colour of the world point each valid depth pixel sees, with
+    sensor noise (sigma 1.5 levels); black where the depth is invalid."""
+    frames = range(stream.n_frames) if frames is None else frames
+    rng = np.random.default_rng(seed)
+    fx, fy, cx, cy = stream.intrinsics
+    W, H = stream.width, stream.height
+    xs = (np.arange(W, dtype=np.float64) - cx) / fx
+    ys = (np.arange(H, dtype=np.float64) - cy) / fy
+    out = np.zeros((len(frames), H, W, 4), np.uint8)
+    for i, f in enumerate(frames):
+        d = stream.depth[f].astype(np.float64)
+        ok = np.isfinite(d) & (d > 0)
+        dd = np.where(ok, d, 0.0)
+        R, o = stream.T_wc[f][:3, :3], stream.T_wc[f][:3, 3]
+        q = np.stack([xs[None, :] * dd, ys[:, None] * dd, dd], -1)
+        P = q @ R.T + o
+        c = 128.0 + 110.0 * np.sin(P @ _CLR_DIR.T * (2.0 * np.pi / 1.6) + _CLR_PHASE)
+        c = np.clip(np.rint(c + rng.standard_normal(c.shape) * 1.5), 0, 255)
+        out[i, ..., :3] = np.where(ok[..., None], c, 0).astype(np.uint8)
+    return out
+
+
 def make_stream(name: str, n_frames: int | None = None, seed: int | None = None,
                 noise: bool = True, cache: bool = True) -> Stream:
     """Seeded synthetic stream for a named workload ("tiny", "vga", "large", "room").
