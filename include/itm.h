@@ -169,6 +169,47 @@ itm_status itm_expected_depths(itm_scene *scene, const itm_intrinsics *K, const 
 itm_status itm_export_blocks(itm_scene *scene, int32_t *coords, float *sdf, float *w,
                              int64_t capacity, int64_t *n_blocks);
 
+/* ---- Colour voxels (section "Framework Flexibility": a voxel may carry a colour
+ * and a colour weight beside F and W; section "Integration": the colour update is
+ * the same running average, fed by the registered colour image).
+ * Colour voxels: 4 bytes each, (r, g, b, colour weight), one per depth voxel. */
+
+/* Allocate the scene's colour voxels (all zero) on the device; a no-op when
+ * already enabled.  Blocks fused before this call keep colour weight 0.
+ * ITM_ERR_OOM when the device memory (vba capacity * 2 KiB) is not there.
+ * Synchronises the stream. */
+itm_status itm_scene_enable_colour(itm_scene *scene);
+
+/* itm_integrate with a colour image:
+ *   rgbx  DEVICE pointer, K->height * K->width * 4 bytes (4-byte aligned),
+ *         row-major (r, g, b, unused), registered to the depth image
+ * Depth voxels are updated exactly as by itm_integrate.  A voxel whose depth is
+ * updated and whose projective distance d - z is at most mu also takes the
+ * colour of its depth pixel: each channel c <- (cw c + c_new) / (cw + 1) in
+ * exact integer arithmetic rounded half to even, cw <- min(cw + 1, min(max_w,
+ * 255)).  ITM_ERR_ARG when colour is not enabled.  Asynchronous. */
+itm_status itm_integrate_colour(itm_scene *scene, const float *depth, const uint8_t *rgbx,
+                                const itm_intrinsics *K, const double *T_wc);
+
+/* itm_raycast that also renders colour:
+ *   out_rgbx  DEVICE pointer, K->height * K->width * 4 bytes (4-byte aligned):
+ *             at a hit, (r, g, b, 255) of the voxel nearest to the hit point
+ *             (lattice point floor(p / s + 1/2)) when its block is allocated,
+ *             else zeros; zeros at a miss.
+ * Points and normals are those itm_raycast writes.  ITM_ERR_ARG when colour is
+ * not enabled.  Asynchronous. */
+itm_status itm_raycast_colour(itm_scene *scene, const itm_intrinsics *K, const double *T_wc,
+                              float *out_pts, float *out_normals, uint8_t *out_rgbx);
+
+/* Copy the colour voxels of the allocated blocks to the host, in the block
+ * order of itm_export_blocks:
+ *   rgbw      HOST uint8[capacity * 512 * 4] or NULL to only count;
+ *             (r, g, b, colour weight) per voxel, voxel order lx + 8 ly + 64 lz
+ *   capacity  blocks the buffer holds; ITM_ERR_ARG when smaller than the count
+ *   n_blocks  HOST int64 out: number of allocated blocks
+ * ITM_ERR_ARG when colour is not enabled.  Synchronises the stream. */
+itm_status itm_export_colour(itm_scene *scene, uint8_t *rgbw, int64_t capacity, int64_t *n_blocks);
+
 /* Counters of the scene (synchronises the stream). */
 itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
 

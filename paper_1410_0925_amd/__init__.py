@@ -59,7 +59,8 @@ EXPORTED = ("itm_scene_create", "itm_scene_create_ex", "itm_scene_destroy", "itm
             "itm_refiner_get_params", "itm_refiner_forward", "itm_refiner_gradient",
             "itm_refiner_train_step", "itm_gather_blocks", "itm_scene_set_refiner",
             "itm_export_blocks_refined", "itm_scene_set_search_range", "itm_expected_depths",
-            "itm_track_default_params", "itm_track", "itm_icp_system")
+            "itm_track_default_params", "itm_track", "itm_icp_system",
+            "itm_scene_enable_colour", "itm_integrate_colour", "itm_raycast_colour", "itm_export_colour")
 ITM_REFINE_PARAMS = 27712
 
 
@@ -101,6 +102,10 @@ def lib():
                                     C.POINTER(itm_track_params), _P, C.POINTER(itm_track_info)]),
             "itm_icp_system": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), C.c_int32, _P, _P, _P, _P,
                                          C.c_float, _P]),
+            "itm_scene_enable_colour": (C.c_int, [_P]),
+            "itm_integrate_colour": (C.c_int, [_P, _P, _P, C.POINTER(itm_intrinsics), _P]),
+            "itm_raycast_colour": (C.c_int, [_P, C.POINTER(itm_intrinsics), _P, _P, _P, _P]),
+            "itm_export_colour": (C.c_int, [_P, _P, C.c_int64, C.POINTER(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -184,6 +189,37 @@ def itm_raycast(h, K, T_wc, out_pts, out_normals):
     q = _dev(out_normals, "torch.float32", n)
     T, Tp = _pose(T_wc)
     _check(lib().itm_raycast(h, C.byref(Ki), Tp, p, q))
+
+
+def itm_scene_enable_colour(h):
+    _check(lib().itm_scene_enable_colour(h))
+
+
+def itm_integrate_colour(h, depth, rgbx, K, T_wc):
+    Ki = _intr(K)
+    ptr = _dev(depth, "torch.float32", Ki.width * Ki.height)
+    c = _dev(rgbx, "torch.uint8", 4 * Ki.width * Ki.height)
+    T, Tp = _pose(T_wc)
+    _check(lib().itm_integrate_colour(h, ptr, c, C.byref(Ki), Tp))
+
+
+def itm_raycast_colour(h, K, T_wc, out_pts, out_normals, out_rgbx):
+    Ki = _intr(K)
+    n = Ki.width * Ki.height * 4
+    p = _dev(out_pts, "torch.float32", n)
+    q = _dev(out_normals, "torch.float32", n)
+    c = _dev(out_rgbx, "torch.uint8", n)
+    T, Tp = _pose(T_wc)
+    _check(lib().itm_raycast_colour(h, C.byref(Ki), Tp, p, q, c))
+
+
+def itm_export_colour(h):
+    n = C.c_int64(0)
+    _check(lib().itm_export_colour(h, None, 0, C.byref(n)))
+    m = n.value
+    rgbw = np.empty((m, 512, 4), np.uint8)
+    _check(lib().itm_export_colour(h, rgbw.ctypes.data_as(_P), m, C.byref(n)))
+    return rgbw
 
 
 def itm_scene_set_search_range(h, enable, tile_capacity=0):
@@ -437,6 +473,32 @@ class Scene:
         self._sync_stream()
         itm_raycast(self.h, Ki, T_wc, out_pts, out_normals)
         return out_pts, out_normals
+
+    def enable_colour(self):
+        """Give every voxel a colour (r, g, b) and a colour weight."""
+        self._sync_stream()
+        itm_scene_enable_colour(self.h)
+
+    def integrate_colour(self, depth, rgbx, K, T_wc):
+        """Fuse a depth frame and its registered colour image (uint8 [H, W, 4])."""
+        self._sync_stream()
+        itm_integrate_colour(self.h, depth, rgbx, K, T_wc)
+
+    def raycast_colour(self, K, T_wc):
+        """Points, normals and colours (uint8 [H, W, 4]) rendered at T_wc."""
+        import torch
+        Ki = _intr(K)
+        pts = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
+        nrm = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
+        rgb = torch.empty((Ki.height, Ki.width, 4), dtype=torch.uint8, device="cuda")
+        self._sync_stream()
+        itm_raycast_colour(self.h, Ki, T_wc, pts, nrm, rgb)
+        return pts, nrm, rgb
+
+    def export_colour(self):
+        """Colour voxels [n, 512, 4] (r, g, b, colour weight) in export order."""
+        self._sync_stream()
+        return itm_export_colour(self.h)
 
     def set_search_range(self, enable=True, tile_capacity=0):
         """Raycast inside each pixel's expected depth range (on) or over

@@ -84,6 +84,23 @@ hipError_t launch_export_gather(int fmt, const void *sdf, const void *w, const i
     return hipGetLastError();
 }
 
+// export of colour voxels: the listed blocks' 512 x 4 bytes, packed in list order
+__global__ __launch_bounds__(256) void k_export_colour(const uchar4 *clr, const int32_t *blocks, int64_t n,
+                                                       uchar4 *out)
+{
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int64_t src = (int64_t)blocks[i] * kBlockVox, dst = i * kBlockVox;
+        for (int l = threadIdx.x; l < kBlockVox; l += blockDim.x) out[dst + l] = clr[src + l];
+    }
+}
+
+hipError_t launch_export_colour(const uchar4 *clr, const int32_t *blocks, int64_t n, uchar4 *out, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(n, 1), 4096);
+    k_export_colour<<<grid, 256, 0, st>>>(clr, blocks, n, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_init(Bucket *b, int32_t *head, int64_t nb, Excess *x, int64_t nx, uint32_t *stamp,
                        int64_t nstamp, unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
                        Counters *cnt, int fmt, void *sdf, void *w, int64_t n_vox, hipStream_t st)

@@ -102,7 +102,28 @@ struct Group4<ITM_VOX_S16U8> {
 };
 
 // one visible block (entry e) by one wave; returns the lane's updated voxels
-template <int FMT>
+// Colour sample of a voxel (section "Framework Flexibility" gives the voxel's
+// RGB and colour weight; the update is the library's reading): each channel keeps
+// the running average of its samples rounded to the nearest integer, ties to
+// even, in exact integer arithmetic; the weight counts samples up to cap.
+__device__ __forceinline__ uchar4 colour_step(uchar4 c, uchar4 s, int cap)
+{
+    const int w = c.w, den = w + 1;
+    int ch[3] = {c.x, c.y, c.z};
+    const int smp[3] = {s.x, s.y, s.z};
+#pragma unroll
+    for (int k = 0; k < 3; k++) {
+        const int num = w * ch[k] + smp[k];
+        int q = num / den;
+        const int r2 = 2 * (num - q * den);
+        if (r2 > den || (r2 == den && (q & 1))) q++;
+        ch[k] = q;
+    }
+    return make_uchar4((unsigned char)ch[0], (unsigned char)ch[1], (unsigned char)ch[2],
+                       (unsigned char)min(w + 1, cap));
+}
+
+template <int FMT, bool CLR>
 __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, int32_t e, int lane)
 {
     const FrameGeom &g = a.fg;
@@ -130,13 +151,21 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
     Group4<FMT> vg[2];
     vg[0].load(a.sdf, a.w, vbase + 4 * lane);
     vg[1].load(a.sdf, a.w, vbase + 4 * lane + 256);
+    // colour voxels: 4 x 4 bytes per group, loaded with the voxels
+    uint4 cg[2];
+    if (CLR) {
+        cg[0] = *reinterpret_cast<const uint4 *>(a.clr + vbase + 4 * lane);
+        cg[1] = *reinterpret_cast<const uint4 *>(a.clr + vbase + 4 * lane + 256);
+    }
+    const int ccap = min((int)g.max_w_f, 255);
     uint32_t n_upd = 0;
 #pragma unroll
     for (int grp = 0; grp < 2; grp++) {
         const int li0 = 4 * lane + 256 * grp;
         const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
         float eta[4];
-        uint32_t upd = 0;
+        int pix[4];
+        uint32_t upd = 0, cupd = 0;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const float fx_ = (float)((li0 & 7) + j);
@@ -154,12 +183,14 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
             const float x = g.fx * p[0] / p[2] + g.cx;
             const float y = g.fy * p[1] / p[2] + g.cy;
             if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
-            const float d = a.depth[(int)(x + 0.5f) + (int)(y + 0.5f) * g.W];
+            pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
+            const float d = a.depth[pix[j]];
             if (!(d > 0.0f) || isinf(d)) continue;
             const float e32 = (d - hi[2]) - (lo[2] + dl2);
             if (e32 < -mu) continue;
             eta[j] = e32;
             upd |= 1u << j;
+            if (CLR && e32 <= mu) cupd |= 1u << j;   // inside the band: a colour sample
         }
         if (upd) {
             Group4<FMT> &v = vg[grp];
@@ -175,6 +206,16 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
             }
             v.store(a.sdf, a.w, vbase + li0);
             n_upd += __builtin_popcount(upd);
+            if (CLR && cupd) {
+                uint32_t c4[4] = {cg[grp].x, cg[grp].y, cg[grp].z, cg[grp].w};
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    if (!(cupd & (1u << j))) continue;
+                    const uchar4 c = colour_step(__builtin_bit_cast(uchar4, c4[j]), a.rgbx[pix[j]], ccap);
+                    c4[j] = __builtin_bit_cast(uint32_t, c);
+                }
+                *reinterpret_cast<uint4 *>(a.clr + vbase + li0) = make_uint4(c4[0], c4[1], c4[2], c4[3]);
+            }
         }
     }
     return n_upd;
@@ -312,7 +353,7 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
 // workgroups), then the overflow segment.  The record is loaded together with
 // the stripe's counter -- it lies inside the stripe's storage whatever the
 // count -- so the two take one memory round instead of two.
-template <int FMT>
+template <int FMT, bool CLR>
 __global__ __launch_bounds__(256) void k_integrate(FuseArgs a)
 {
     __shared__ unsigned long long s_red[2][4];
@@ -325,7 +366,7 @@ __global__ __launch_bounds__(256) void k_integrate(FuseArgs a)
         for (int i = gw >> 5; i < a.list.cap; i += step) {   // uniform over the wave
             const VisRec r = a.list.rec[(int64_t)stripe * a.list.cap + i];
             if (i >= n) break;
-            n_upd += integrate_block<FMT>(a, r.key, r.e, lane);
+            n_upd += integrate_block<FMT, CLR>(a, r.key, r.e, lane);
             n_blk++;
         }
     }
@@ -333,7 +374,7 @@ __global__ __launch_bounds__(256) void k_integrate(FuseArgs a)
         const int n = a.list.cnt[32 * 32];
         for (int i = gw; i < n; i += nw) {
             const VisRec r = a.list.rec[(int64_t)32 * a.list.cap + i];
-            n_upd += integrate_block<FMT>(a, r.key, r.e, lane);
+            n_upd += integrate_block<FMT, CLR>(a, r.key, r.e, lane);
             n_blk++;
         }
     }
@@ -368,10 +409,14 @@ hipError_t launch_alloc(const FuseArgs &a, hipStream_t st)
 
 hipError_t launch_integrate(int fmt, const FuseArgs &a, int grid, hipStream_t st)
 {
-    switch (fmt) {
-    case ITM_VOX_F32: k_integrate<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
-    case ITM_VOX_F16: k_integrate<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;
-    default: k_integrate<ITM_VOX_S16U8><<<grid, 256, 0, st>>>(a); break;
+    const bool clr = a.clr && a.rgbx;
+    switch (fmt * 2 + (clr ? 1 : 0)) {
+    case 2 * ITM_VOX_F32: k_integrate<ITM_VOX_F32, false><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_F32 + 1: k_integrate<ITM_VOX_F32, true><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_F16: k_integrate<ITM_VOX_F16, false><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_F16 + 1: k_integrate<ITM_VOX_F16, true><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_S16U8 + 1: k_integrate<ITM_VOX_S16U8, true><<<grid, 256, 0, st>>>(a); break;
+    default: k_integrate<ITM_VOX_S16U8, false><<<grid, 256, 0, st>>>(a); break;
     }
     return hipGetLastError();
 }

@@ -272,12 +272,16 @@ struct FuseArgs {
     int32_t n_clear;
     void *sdf;
     void *w;
+    uchar4 *clr;                  // colour voxels (r, g, b, colour weight), or nullptr
+    const uchar4 *rgbx;           // this frame's registered colour image, or nullptr
     Counters *cnt;
 };
 
 struct RaycastArgs {
     FrameGeom fg;
     HashView h;
+    const uchar4 *clr;            // colour voxels, or nullptr
+    uchar4 *rgb_out;              // per pixel: colour of the hit's nearest voxel, or nullptr
     const void *sdf;
     float4 *pts;
     float4 *nrm;
@@ -340,6 +344,7 @@ hipError_t launch_integrate(int fmt, const FuseArgs &a, int grid, hipStream_t st
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st);
 hipError_t launch_export_gather(int fmt, const void *sdf, const void *w, const int32_t *blocks, int64_t n,
                                 void *out_sdf, void *out_w, hipStream_t st);
+hipError_t launch_export_colour(const uchar4 *clr, const int32_t *blocks, int64_t n, uchar4 *out, hipStream_t st);
 hipError_t launch_init(Bucket *b, int32_t *head, int64_t nb, Excess *x, int64_t nx, uint32_t *stamp, int64_t nstamp,
                        unsigned long long *set, int64_t nset, uint32_t *occ, int64_t nocc,
                        Counters *cnt, int fmt, void *sdf, void *w, int64_t n_vox, hipStream_t st);

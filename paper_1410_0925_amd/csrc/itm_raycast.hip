@@ -88,16 +88,23 @@ struct Cube {
     }
 };
 
-// Voxel reads of a Cube: a short select of the voxel's block, then one load (an
-// absent block reads as F = 1)
+// the block of voxel v among a Cube's (-1 when absent)
 template <int FMT>
-__device__ __forceinline__ float cube_F(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int vx, int vy, int vz)
+__device__ __forceinline__ int32_t cube_block(const Cube<FMT> &cb, int vx, int vy, int vz)
 {
     const bool ex = (vx >> 3) != cb.bx0, ey = (vy >> 3) != cb.by0, ez = (vz >> 3) != cb.bz0;
     const int32_t a0 = ex ? cb.p[1] : cb.p[0], a1 = ex ? cb.p[3] : cb.p[2];
     const int32_t a2 = ex ? cb.p[5] : cb.p[4], a3 = ex ? cb.p[7] : cb.p[6];
     const int32_t b0 = ey ? a1 : a0, b1 = ey ? a3 : a2;
-    const int32_t ptr = ez ? b1 : b0;
+    return ez ? b1 : b0;
+}
+
+// Voxel reads of a Cube: a short select of the voxel's block, then one load (an
+// absent block reads as F = 1)
+template <int FMT>
+__device__ __forceinline__ float cube_F(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int vx, int vy, int vz)
+{
+    const int32_t ptr = cube_block(cb, vx, vy, vz);
     if (ptr < 0) return 1.0f;
     return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (int32_t)((vx & 7) | (vy & 7) << 3 | (vz & 7) << 6)]);
 }
@@ -294,6 +301,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         }
     }
     float4 P = make_float4(0.f, 0.f, 0.f, 0.f), N = make_float4(0.f, 0.f, 0.f, 0.f);
+    uchar4 C = make_uchar4(0, 0, 0, 0);
     if (state == RC_BEHIND) {
         const auto *sdf = (const typename Vox<FMT>::S *)a.sdf;
         // One block neighbourhood for the whole final phase: the blocks of voxels
@@ -332,6 +340,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         stencil(cb, sdf, ix, iy, iz, ix == jx && iy == jy && iz == jz, Fc, Ex, Ey, Ez);
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
         gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
+        if (a.rgb_out) {   // colour of the final point's nearest voxel (held by the Cube)
+            const int nx = (int)floorf(qx + 0.5f), ny = (int)floorf(qy + 0.5f), nz = (int)floorf(qz + 0.5f);
+            const int32_t p = cube_block(cb, nx, ny, nz);
+            if (p >= 0) {
+                const uchar4 c = a.clr[(int64_t)p * kBlockVox + ((nx & 7) | (ny & 7) << 3 | (nz & 7) << 6)];
+                C = make_uchar4(c.x, c.y, c.z, 255);
+            }
+        }
         // the hit in metres, (o + t d) s in binary64 from the march's binary32 terms
         P = make_float4((float)(g.s * ((double)ox + (double)t * (double)dx)),
                         (float)(g.s * ((double)oy + (double)t * (double)dy)),
@@ -344,6 +360,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     }
     a.pts[pix] = P;
     a.nrm[pix] = N;
+    if (a.rgb_out) a.rgb_out[pix] = C;
 }
 
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st)

@@ -105,6 +105,8 @@ struct itm_scene {
     double *trk_pose = nullptr;       // [16] current estimate, then [32] the last system
     int32_t *trk_flags = nullptr;     // [kTrackLevels] stop flags, then the step count
 
+    uchar4 *clr = nullptr;            // [vba_cap][512] colour voxels, allocated on enable
+
     bool prof = false;
     std::vector<hipEvent_t> ev;     // 2 per slot
     std::vector<int> ev_kernel;
@@ -141,6 +143,7 @@ void release(itm_scene *sc)
     (void)hipFree(sc->trk_part);
     (void)hipFree(sc->trk_pose);
     (void)hipFree(sc->trk_flags);
+    (void)hipFree(sc->clr);
     delete sc;
 }
 
@@ -433,9 +436,15 @@ itm_status itm_set_stream(itm_scene *sc, void *hip_stream)
     return ITM_OK;
 }
 
-itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics *K, const double *T_wc)
+}  // extern "C"
+
+namespace {
+
+// one frame: allocation, visible list and integration; with rgbx set, the
+// colour voxels too
+itm_status integrate_frame(itm_scene *sc, const float *depth, const uchar4 *rgbx, const itm_intrinsics *K,
+                           const double *T_wc)
 {
-    if (!sc || !depth) return fail(ITM_ERR_ARG, "NULL scene or depth");
     FrameGeom g;
     if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
     const HashView h = hash_view(sc);
@@ -472,6 +481,8 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
         }
         a.sdf = sc->sdf;
         a.w = sc->w;
+        a.clr = rgbx ? sc->clr : nullptr;
+        a.rgbx = rgbx;
         a.cnt = sc->cnt;
     }
     {
@@ -511,10 +522,9 @@ itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics
     return ITM_OK;
 }
 
-itm_status itm_raycast(itm_scene *sc, const itm_intrinsics *K, const double *T_wc, float *out_pts,
-                       float *out_normals)
+itm_status raycast_frame(itm_scene *sc, const itm_intrinsics *K, const double *T_wc, float *out_pts,
+                         float *out_normals, uchar4 *out_rgbx)
 {
-    if (!sc || !out_pts || !out_normals) return fail(ITM_ERR_ARG, "NULL scene or output");
     if (((uintptr_t)out_pts | (uintptr_t)out_normals) & 15u)
         return fail(ITM_ERR_ARG, "outputs must be 16-byte aligned");
     FrameGeom g;
@@ -526,12 +536,65 @@ itm_status itm_raycast(itm_scene *sc, const itm_intrinsics *K, const double *T_w
     a.sdf = sc->sdf;
     a.pts = reinterpret_cast<float4 *>(out_pts);
     a.nrm = reinterpret_cast<float4 *>(out_normals);
+    a.clr = out_rgbx ? sc->clr : nullptr;
+    a.rgb_out = out_rgbx;
     a.rb = RangeBins{};
     a.list = vis_list(sc, last_parity(sc));
     if (sc->range_on)
         if (itm_status st = bins_for_pose(sc, K, T_wc, g, &a.rb)) return st;
     HIP_TRY(launch_raycast(sc->fmt, a, sc->stream));
     return ITM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+itm_status itm_integrate(itm_scene *sc, const float *depth, const itm_intrinsics *K, const double *T_wc)
+{
+    if (!sc || !depth) return fail(ITM_ERR_ARG, "NULL scene or depth");
+    return integrate_frame(sc, depth, nullptr, K, T_wc);
+}
+
+itm_status itm_raycast(itm_scene *sc, const itm_intrinsics *K, const double *T_wc, float *out_pts,
+                       float *out_normals)
+{
+    if (!sc || !out_pts || !out_normals) return fail(ITM_ERR_ARG, "NULL scene or output");
+    return raycast_frame(sc, K, T_wc, out_pts, out_normals, nullptr);
+}
+
+itm_status itm_scene_enable_colour(itm_scene *sc)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    if (sc->clr) return ITM_OK;
+    const size_t bytes = sizeof(uchar4) * kBlockVox * (size_t)sc->vba_cap;
+    if (itm_status st = dev_alloc((void **)&sc->clr, bytes, "colour voxels")) return st;
+    hipError_t e = hipMemsetAsync(sc->clr, 0, bytes, sc->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(sc->clr);
+        sc->clr = nullptr;
+        return fail(ITM_ERR_HIP, "colour voxel initialisation failed: %s", hipGetErrorString(e));
+    }
+    return ITM_OK;
+}
+
+itm_status itm_integrate_colour(itm_scene *sc, const float *depth, const uint8_t *rgbx, const itm_intrinsics *K,
+                                const double *T_wc)
+{
+    if (!sc || !depth || !rgbx) return fail(ITM_ERR_ARG, "NULL scene, depth or colour image");
+    if (!sc->clr) return fail(ITM_ERR_ARG, "colour is not enabled on this scene");
+    if ((uintptr_t)rgbx & 3u) return fail(ITM_ERR_ARG, "colour image must be 4-byte aligned");
+    return integrate_frame(sc, depth, reinterpret_cast<const uchar4 *>(rgbx), K, T_wc);
+}
+
+itm_status itm_raycast_colour(itm_scene *sc, const itm_intrinsics *K, const double *T_wc, float *out_pts,
+                              float *out_normals, uint8_t *out_rgbx)
+{
+    if (!sc || !out_pts || !out_normals || !out_rgbx) return fail(ITM_ERR_ARG, "NULL scene or output");
+    if (!sc->clr) return fail(ITM_ERR_ARG, "colour is not enabled on this scene");
+    if ((uintptr_t)out_rgbx & 3u) return fail(ITM_ERR_ARG, "colour output must be 4-byte aligned");
+    return raycast_frame(sc, K, T_wc, out_pts, out_normals, reinterpret_cast<uchar4 *>(out_rgbx));
 }
 
 itm_status itm_scene_set_search_range(itm_scene *sc, int32_t enable, int32_t tile_capacity)
@@ -709,6 +772,37 @@ itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *
             }
         }
     }
+    return ITM_OK;
+}
+
+itm_status itm_export_colour(itm_scene *sc, uint8_t *rgbw, int64_t capacity, int64_t *n_blocks)
+{
+    if (!sc || !n_blocks) return fail(ITM_ERR_ARG, "NULL scene or n_blocks");
+    if (!sc->clr) return fail(ITM_ERR_ARG, "colour is not enabled on this scene");
+    std::vector<BlockRec> recs;
+    if (itm_status st = collect_blocks(sc, recs)) return st;
+    const int64_t n = (int64_t)recs.size();
+    *n_blocks = n;
+    if (!rgbw || n == 0) return ITM_OK;
+    if (capacity < n) return fail(ITM_ERR_ARG, "capacity %lld < %lld blocks", (long long)capacity, (long long)n);
+    std::vector<int32_t> blk(n);
+    for (int64_t i = 0; i < n; i++) blk[i] = recs[i].blk;
+    int32_t *d_blk = nullptr;
+    uchar4 *d_c = nullptr;
+    itm_status st = dev_alloc((void **)&d_blk, sizeof(int32_t) * n, "export list");
+    if (!st) st = dev_alloc((void **)&d_c, sizeof(uchar4) * kBlockVox * n, "export colour");
+    hipError_t e = hipSuccess;
+    if (!st) {
+        e = hipMemcpyAsync(d_blk, blk.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, sc->stream);
+        if (e == hipSuccess) e = launch_export_colour(sc->clr, d_blk, n, d_c, sc->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(rgbw, d_c, sizeof(uchar4) * kBlockVox * n, hipMemcpyDeviceToHost, sc->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    }
+    (void)hipFree(d_blk);
+    (void)hipFree(d_c);
+    if (st) return st;
+    if (e != hipSuccess) return fail(ITM_ERR_HIP, "colour export failed: %s", hipGetErrorString(e));
     return ITM_OK;
 }
 
