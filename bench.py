@@ -29,10 +29,10 @@ SDF_BYTES = {"f32": 4, "f16": 2, "s16u8": 2}
 VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 
 
-# Hardware byte counters of the kernels on this workload, KiB per dispatch,
-# averaged over the bench's timed frames 10..299 (search range on), from
+# Hardware byte counters of the depth-only kernels on this workload, KiB per
+# dispatch, averaged over the bench's timed frames 10..299 (search range on), from
 #   rocprofv3 --pmc FETCH_SIZE (resp. WRITE_SIZE) -- python3 bench.py
-#   --no-cpu-baseline --no-learned --no-events --calib-copy-mb 256
+#   --no-cpu-baseline --no-learned --no-colour --no-events --calib-copy-mb 256
 # (summaries under profiles/).  FETCH_SIZE counts 64 B per read request while
 # these kernels' read requests are 128 B (TCC_EA0_RDREQ_128B): the reference
 # elementwise kernel that reads 256 MiB reports 131,088 KiB, hence the factor 2;
@@ -41,9 +41,9 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 # reports traffic null.
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.9, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga"): {"fetch": 1022.0, "write": 1207.9, "src": "09c47ca90418c23a"},
-    ("integrate", "f32", "vga"): {"fetch": 10011.2, "write": 14770.5, "src": "09c47ca90418c23a"},
-    ("raycast", "f32", "vga"): {"fetch": 7519.4, "write": 9600.0, "src": "c62d787c89435e25"},
+    ("alloc", "f32", "vga"): {"fetch": 1022.1, "write": 1208.2, "src": "054ff348adb1e4eb"},
+    ("integrate", "f32", "vga"): {"fetch": 10011.9, "write": 14770.6, "src": "054ff348adb1e4eb"},
+    ("raycast", "f32", "vga"): {"fetch": 7399.3, "write": 9600.0, "src": "e740fd7bfa44f45f"},
 }
 
 
@@ -181,6 +181,61 @@ def track_leg(itm, torch, sc, st, depth, K, f, calls, cpu):
     return out
 
 
+def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps):
+    """Colour voxels (section "Framework Flexibility"; the colour update of
+    section "Integration"): the same frames fused with their registered colour
+    images (itm_integrate_colour) and raycast with colour (itm_raycast_colour),
+    on a scene of its own.  Algorithmic bytes beyond the depth-only kernels:
+    integration reads and writes the 4-byte colour voxel of every updated voxel
+    and reads the colour image; the raycast writes a 4-byte colour per pixel and
+    reads one colour voxel per hit."""
+    from synth import colour_frames
+    W, H = K[4], K[5]
+    rgb = torch.from_numpy(colour_frames(st, range(warmup + steps))).cuda()
+    pts = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(pts)
+    crgb = torch.empty((H, W, 4), dtype=torch.uint8, device="cuda")
+    sc = itm.Scene.from_params(st.params, fmt=fmt)
+    sc.enable_colour()
+    sc.set_search_range(ranged)
+    for f in range(warmup):
+        sc.integrate_colour(depth[f], rgb[f], K, st.T_wc[f])
+        sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
+    torch.cuda.synchronize()
+    s0 = sc.stats()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        f = warmup + i
+        sc.integrate_colour(depth[f], rgb[f], K, st.T_wc[f])
+        sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s1 = sc.stats()
+    # per-kernel times: a second pass over the last frames with events
+    sc.profile_read()
+    sc.profile(True)
+    for f in range(warmup + steps - 10, warmup + steps):
+        sc.integrate_colour(depth[f], rgb[f], K, st.T_wc[f])
+        sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
+    sc.profile(False)
+    prof = sc.profile_read()
+    sc.close()
+    vis = s1["n_visible_total"] - s0["n_visible_total"]
+    upd = s1["n_updated_total"] - s0["n_updated_total"]
+    out = {"frames": f"{warmup}..{warmup + steps - 1}", "ms_per_step": wall * 1e3 / steps,
+           "value": vis * 512 / wall, "unit": "voxels/s", "kernels": {}}
+    extra = {"integrate": 8.0 * upd / steps + 4.0 * W * H, "raycast": 8.0 * W * H}
+    for name in ("alloc", "integrate", "raycast"):
+        ms, n = prof[name]
+        if n == 0:
+            continue
+        b = kernel_bytes(name, fmt, W, H, steps, vis, upd, s1["n_entries"]) + extra.get(name, 0.0)
+        gbs = b / (ms / n * 1e-3) / 1e9
+        out["kernels"][name] = {"avg_us": round(ms / n * 1e3, 3), "launches_timed": n, "bytes_per_launch": round(b),
+                                "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def cpu_baseline(stream, seconds, search_range):
     """The CPU oracle (allocation + integration, plain loops) on the first frames
     of the same stream until about `seconds` of work, then one raycast."""
@@ -226,6 +281,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the refiner timing leg")
     ap.add_argument("--no-track", action="store_true", help="skip the depth tracker timing leg")
+    ap.add_argument("--no-colour", action="store_true", help="skip the colour voxel timing leg")
+    ap.add_argument("--colour-steps", type=int, default=None,
+                    help="frames timed in the colour leg (default: the same frames as the main loop)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, copy a buffer of this size once "
@@ -347,6 +405,10 @@ def main():
         log("depth tracker: last frame against the raycast at the frame before")
         out["track"] = track_leg(itm, torch, sc, st, depth, K, args.warmup + args.steps - 1, 20,
                                  not args.no_cpu_baseline)
+    if not args.no_colour:
+        log("colour voxels: fusion and raycast with colour")
+        out["colour"] = colour_leg(itm, torch, st, depth, K, args.fmt, ranged, args.warmup,
+                                   min(args.colour_steps or args.steps, args.steps))
     if not args.no_learned:
         log("learned form: refiner training steps and forward passes")
         out["learned"] = learned_leg(itm, torch)

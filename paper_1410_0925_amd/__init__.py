@@ -484,13 +484,16 @@ class Scene:
         self._sync_stream()
         itm_integrate_colour(self.h, depth, rgbx, K, T_wc)
 
-    def raycast_colour(self, K, T_wc):
+    def raycast_colour(self, K, T_wc, pts=None, nrm=None, rgb=None):
         """Points, normals and colours (uint8 [H, W, 4]) rendered at T_wc."""
         import torch
         Ki = _intr(K)
-        pts = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
-        nrm = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
-        rgb = torch.empty((Ki.height, Ki.width, 4), dtype=torch.uint8, device="cuda")
+        if pts is None:
+            pts = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
+        if nrm is None:
+            nrm = torch.empty((Ki.height, Ki.width, 4), dtype=torch.float32, device="cuda")
+        if rgb is None:
+            rgb = torch.empty((Ki.height, Ki.width, 4), dtype=torch.uint8, device="cuda")
         self._sync_stream()
         itm_raycast_colour(self.h, Ki, T_wc, pts, nrm, rgb)
         return pts, nrm, rgb

@@ -177,7 +177,7 @@ __device__ __forceinline__ void gradient(const float Fc[8], const float Ex[2][4]
     }
 }
 
-template <int FMT>
+template <int FMT, bool CLR>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raycast(RaycastArgs a)
 {
     const FrameGeom &g = a.fg;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         stencil(cb, sdf, ix, iy, iz, ix == jx && iy == jy && iz == jz, Fc, Ex, Ey, Ez);
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
         gradient(Fc, Ex, Ey, Ez, qx - fx, qy - fy, qz - fz, gx, gy, gz);
-        if (a.rgb_out) {   // colour of the final point's nearest voxel (held by the Cube)
+        if (CLR) {   // colour of the final point's nearest voxel (held by the Cube)
             const int nx = (int)floorf(qx + 0.5f), ny = (int)floorf(qy + 0.5f), nz = (int)floorf(qz + 0.5f);
             const int32_t p = cube_block(cb, nx, ny, nz);
             if (p >= 0) {
@@ -360,16 +360,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     }
     a.pts[pix] = P;
     a.nrm[pix] = N;
-    if (a.rgb_out) a.rgb_out[pix] = C;
+    if (CLR) a.rgb_out[pix] = C;
 }
 
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st)
 {
     const int grid = xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16));
-    switch (fmt) {
-    case ITM_VOX_F32: k_raycast<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
-    case ITM_VOX_F16: k_raycast<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;
-    default: k_raycast<ITM_VOX_S16U8><<<grid, 256, 0, st>>>(a); break;
+    // the colour variant is a kernel of its own: the depth-only raycast carries
+    // no colour code
+    const bool clr = a.clr && a.rgb_out;
+    switch (fmt * 2 + (clr ? 1 : 0)) {
+    case 2 * ITM_VOX_F32: k_raycast<ITM_VOX_F32, false><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_F32 + 1: k_raycast<ITM_VOX_F32, true><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_F16: k_raycast<ITM_VOX_F16, false><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_F16 + 1: k_raycast<ITM_VOX_F16, true><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_S16U8 + 1: k_raycast<ITM_VOX_S16U8, true><<<grid, 256, 0, st>>>(a); break;
+    default: k_raycast<ITM_VOX_S16U8, false><<<grid, 256, 0, st>>>(a); break;
     }
     return hipGetLastError();
 }
