@@ -41,9 +41,9 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 # reports traffic null.
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.9, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga"): {"fetch": 1022.1, "write": 1208.2, "src": "054ff348adb1e4eb"},
-    ("integrate", "f32", "vga"): {"fetch": 10011.9, "write": 14770.6, "src": "054ff348adb1e4eb"},
-    ("raycast", "f32", "vga"): {"fetch": 7399.3, "write": 9600.0, "src": "e740fd7bfa44f45f"},
+    ("alloc", "f32", "vga"): {"fetch": 1022.1, "write": 1208.0, "src": "137e19f6a7f10858"},
+    ("integrate", "f32", "vga"): {"fetch": 10008.6, "write": 14770.5, "src": "137e19f6a7f10858"},
+    ("raycast", "f32", "vga"): {"fetch": 7396.8, "write": 9600.0, "src": "e740fd7bfa44f45f"},
 }
 
 
@@ -181,7 +181,7 @@ def track_leg(itm, torch, sc, st, depth, K, f, calls, cpu):
     return out
 
 
-def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps):
+def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True, event_every=10):
     """Colour voxels (section "Framework Flexibility"; the colour update of
     section "Integration"): the same frames fused with their registered colour
     images (itm_integrate_colour) and raycast with colour (itm_raycast_colour),
@@ -203,21 +203,21 @@ def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps):
         sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
     torch.cuda.synchronize()
     s0 = sc.stats()
+    sc.profile_read()
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
         f = warmup + i
+        ev = events and i % event_every == 0   # as in the main loop
+        if ev:
+            sc.profile(True)
         sc.integrate_colour(depth[f], rgb[f], K, st.T_wc[f])
         sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
+        if ev:
+            sc.profile(False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     s1 = sc.stats()
-    # per-kernel times: a second pass over the last frames with events
-    sc.profile_read()
-    sc.profile(True)
-    for f in range(warmup + steps - 10, warmup + steps):
-        sc.integrate_colour(depth[f], rgb[f], K, st.T_wc[f])
-        sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
-    sc.profile(False)
     prof = sc.profile_read()
     sc.close()
     vis = s1["n_visible_total"] - s0["n_visible_total"]
@@ -226,7 +226,7 @@ def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps):
            "value": vis * 512 / wall, "unit": "voxels/s", "kernels": {}}
     extra = {"integrate": 8.0 * upd / steps + 4.0 * W * H, "raycast": 8.0 * W * H}
     for name in ("alloc", "integrate", "raycast"):
-        ms, n = prof[name]
+        ms, n = prof.get(name, (0.0, 0))
         if n == 0:
             continue
         b = kernel_bytes(name, fmt, W, H, steps, vis, upd, s1["n_entries"]) + extra.get(name, 0.0)
@@ -408,7 +408,8 @@ def main():
     if not args.no_colour:
         log("colour voxels: fusion and raycast with colour")
         out["colour"] = colour_leg(itm, torch, st, depth, K, args.fmt, ranged, args.warmup,
-                                   min(args.colour_steps or args.steps, args.steps))
+                                   min(args.colour_steps or args.steps, args.steps),
+                                   not args.no_events, args.event_every)
     if not args.no_learned:
         log("learned form: refiner training steps and forward passes")
         out["learned"] = learned_leg(itm, torch)

@@ -151,17 +151,15 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
     Group4<FMT> vg[2];
     vg[0].load(a.sdf, a.w, vbase + 4 * lane);
     vg[1].load(a.sdf, a.w, vbase + 4 * lane + 256);
-    // colour voxels: 4 x 4 bytes per group, loaded with the voxels
-    uint4 cg[2];
-    if (CLR) {
-        cg[0] = *reinterpret_cast<const uint4 *>(a.clr + vbase + 4 * lane);
-        cg[1] = *reinterpret_cast<const uint4 *>(a.clr + vbase + 4 * lane + 256);
-    }
     const int ccap = min((int)g.max_w_f, 255);
     uint32_t n_upd = 0;
 #pragma unroll
     for (int grp = 0; grp < 2; grp++) {
         const int li0 = 4 * lane + 256 * grp;
+        // the group's 4 colour voxels (16 bytes), loaded here rather than with the
+        // depth voxels: fewer live registers keep 5 waves per SIMD
+        uint4 cgg;
+        if (CLR) cgg = *reinterpret_cast<const uint4 *>(a.clr + vbase + li0);
         const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
         float eta[4];
         int pix[4];
@@ -207,7 +205,7 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
             v.store(a.sdf, a.w, vbase + li0);
             n_upd += __builtin_popcount(upd);
             if (CLR && cupd) {
-                uint32_t c4[4] = {cg[grp].x, cg[grp].y, cg[grp].z, cg[grp].w};
+                uint32_t c4[4] = {cgg.x, cgg.y, cgg.z, cgg.w};
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     if (!(cupd & (1u << j))) continue;
@@ -353,8 +351,10 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
 // workgroups), then the overflow segment.  The record is loaded together with
 // the stripe's counter -- it lies inside the stripe's storage whatever the
 // count -- so the two take one memory round instead of two.
+// (5 waves per SIMD: the grid's 5 workgroups per CU then run in one round; the
+// colour variant is held to 96 registers for it)
 template <int FMT, bool CLR>
-__global__ __launch_bounds__(256) void k_integrate(FuseArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_integrate(FuseArgs a)
 {
     __shared__ unsigned long long s_red[2][4];
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
