@@ -219,20 +219,6 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
     return n_upd;
 }
 
-// The per-frame kernel: allocation and visible list (itm_alloc.hpp) and the
-// integration of the blocks the workgroup owns.
-//   1. housekeeping, every workgroup its share: the previous frame's claim slots
-//      and, with the search range on, the next frame's bin counts are cleared;
-//   2. each thread walks its pixel's band segment, finds or inserts the blocks,
-//      and records them in the workgroup's LDS set;
-//   3. every block of the set is stamped with the frame number; the workgroup
-//      that stamps a block first owns it: it appends it to the visible list and
-//      integrates it -- one wave per block -- so each visible block is
-//      integrated exactly once, by a workgroup that has just touched its bucket;
-//   4. with the search range on, the owned blocks' expected-depth rectangles are
-//      binned by image tile.
-// The list append's atomic is issued before the integration and its result used
-// after it, so its round trip overlaps the voxel work.
 // Allocation and visible list (itm_alloc.hpp), one thread per pixel:
 //   1. housekeeping, every workgroup its share: the previous frame's claim slots
 //      and, with the search range on, the next frame's bin counts are cleared;
