@@ -123,14 +123,79 @@ __device__ __forceinline__ bool set_insert(int32_t *s_e, unsigned long long *s_k
 }
 
 // Expected-depth rectangles of the workgroup's n listed blocks at the frame's
-// pose, appended to the bins of the tiles they overlap.  8 lanes per block take
-// its 8 box corners and merge them with a butterfly; 32 blocks per pass; each of
-// the 8 lanes then takes every 8th tile, so the reservations go out together.
-__device__ inline void bin_blocks(const FrameGeom &g, const RangeBins &rb, const unsigned long long *keys, int n)
+// pose, appended to the bins of the tiles they overlap.  8 lanes per block make
+// its rectangle (block_rect8), 32 blocks per pass.  The blocks a workgroup lists
+// come from its own pixels, so their rectangles share tiles: the (block, tile)
+// pairs are first counted per tile in an LDS table, one global atomic per
+// distinct tile reserves the tile's slots, and the pairs then take consecutive
+// slots (a tile that finds the table full reserves pair by pair).  tab: LDS,
+// 4 * kBinTab ints (tile, pairs, cursor, base); n is uniform.
+constexpr int kBinTab = 256;
+
+__device__ __forceinline__ int bin_tab_slot(int32_t *tab, int tile, bool insert)
 {
+    uint32_t h = ((uint32_t)tile * 2654435761u) >> 24;   // 8 bits: kBinTab slots
+#pragma unroll 1
+    for (int probe = 0; probe < kBinTab; probe++, h = (h + 1) & (kBinTab - 1)) {
+        const int32_t cur = insert ? atomicCAS(&tab[4 * h], -1, tile) : tab[4 * h];
+        if (cur == tile || (insert && cur == -1)) return (int)h;
+        if (cur == -1) return -1;   // lookup: not in the table
+    }
+    return -1;
+}
+
+__device__ inline void bin_blocks(const FrameGeom &g, const RangeBins &rb, const unsigned long long *keys, int n,
+                                  int32_t *tab)
+{
+    const int corner = threadIdx.x & 7;
+    for (int i = threadIdx.x; i < kBinTab; i += blockDim.x) {
+        tab[4 * i] = -1;
+        tab[4 * i + 1] = 0;
+        tab[4 * i + 2] = 0;
+    }
+    __syncthreads();
+    // 1. rectangles; pairs counted per tile (the first pass's rectangle is kept)
+    RangeRect r0;
+    bool ok0 = false;
     for (int base = 0; base < n; base += 32) {   // uniform
         const int j = base + (int)(threadIdx.x >> 3);
-        bin_block8(g, rb, j < n, j < n ? keys[j] : 0ull);
+        RangeRect r;
+        const bool ok = block_rect8(g, j < n, j < n ? keys[j] : 0ull, r);
+        if (base == 0) {
+            r0 = r;
+            ok0 = ok;
+        }
+        if (!ok) continue;
+        int tx0, ty0, ntx, n_tiles;
+        rect_tiles(r, tx0, ty0, ntx, n_tiles);
+        for (int t = corner; t < n_tiles; t += 8) {
+            const int slot = bin_tab_slot(tab, (ty0 + t / ntx) * rb.tw + tx0 + t % ntx, true);
+            if (slot >= 0) atomicAdd(&tab[4 * slot + 1], 1);
+        }
+    }
+    __syncthreads();
+    // 2. one reservation per distinct tile
+    for (int i = threadIdx.x; i < kBinTab; i += blockDim.x) {
+        const int tile = tab[4 * i];
+        if (tile >= 0) tab[4 * i + 3] = atomicAdd(&rb.cnt[tile], tab[4 * i + 1]);
+    }
+    __syncthreads();
+    // 3. the pairs take their slots
+    for (int base = 0; base < n; base += 32) {   // uniform
+        const int j = base + (int)(threadIdx.x >> 3);
+        RangeRect r = r0;
+        bool ok = ok0;
+        if (base > 0) ok = block_rect8(g, j < n, j < n ? keys[j] : 0ull, r);
+        if (!ok) continue;
+        int tx0, ty0, ntx, n_tiles;
+        rect_tiles(r, tx0, ty0, ntx, n_tiles);
+        for (int t = corner; t < n_tiles; t += 8) {
+            const int tile = (ty0 + t / ntx) * rb.tw + tx0 + t % ntx;
+            const int slot = bin_tab_slot(tab, tile, false);
+            const int pos = slot >= 0 ? tab[4 * slot + 3] + atomicAdd(&tab[4 * slot + 2], 1)
+                                      : atomicAdd(&rb.cnt[tile], 1);
+            if (pos < rb.cap) rb.rect[(int64_t)tile * rb.cap + pos] = r;
+        }
     }
 }
 

@@ -329,7 +329,7 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
     // 4. expected-depth rectangles
     if (!a.rb.cnt || n_won == 0) return;   // uniform
     __syncthreads();
-    bin_blocks(g, a.rb, s_k, n_won);
+    bin_blocks(g, a.rb, s_k, n_won, s_e);   // s_e is free again: its entries are in registers
 }
 
 // Integration: one wave per visible block.  Wave gw serves list stripe

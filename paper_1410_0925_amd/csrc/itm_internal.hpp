@@ -496,12 +496,11 @@ __device__ __forceinline__ void rect_tiles(const RangeRect &r, int &tx0, int &ty
     n = ntx * (r.v1 / kTile - ty0 + 1);
 }
 
-// One block's rectangle appended to the bins of the tiles it overlaps by a group
-// of 8 consecutive lanes: lane c = lane & 7 projects box corner c, a butterfly
-// merges the 8, then lane c takes every 8th tile, so the reservations go out
-// together.  valid is uniform over the group.
-__device__ __forceinline__ void bin_block8(const FrameGeom &g, const RangeBins &rb, bool valid,
-                                           unsigned long long key)
+// One block's rectangle by a group of 8 consecutive lanes: lane c = lane & 7
+// projects box corner c and a butterfly merges the 8 (every lane of the group
+// ends with the rectangle).  valid is uniform over the group; false when the
+// block is invalid or covers no pixel.
+__device__ __forceinline__ bool block_rect8(const FrameGeom &g, bool valid, unsigned long long key, RangeRect &r)
 {
     const int corner = threadIdx.x & 7;
     BoxAcc b;
@@ -526,8 +525,18 @@ __device__ __forceinline__ void bin_block8(const FrameGeom &g, const RangeBins &
         c.behind = __shfl_xor((int)b.behind, o, kWave) != 0;
         box_merge(b, c);
     }
+    return valid && box_rect(g, b, r);
+}
+
+// One block's rectangle appended to the bins of the tiles it overlaps by a group
+// of 8 consecutive lanes (block_rect8), then lane c takes every 8th tile, so the
+// reservations go out together.
+__device__ __forceinline__ void bin_block8(const FrameGeom &g, const RangeBins &rb, bool valid,
+                                           unsigned long long key)
+{
+    const int corner = threadIdx.x & 7;
     RangeRect r;
-    if (valid && box_rect(g, b, r)) {
+    if (block_rect8(g, valid, key, r)) {
         int tx0, ty0, ntx, n_tiles;
         rect_tiles(r, tx0, ty0, ntx, n_tiles);
         for (int t = corner; t < n_tiles; t += 8) {
