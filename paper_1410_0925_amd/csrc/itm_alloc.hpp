@@ -105,21 +105,22 @@ __device__ inline int32_t find_or_insert(const FuseArgs &a, int bx, int by, int 
 
 constexpr int kSet = 2048;   // LDS set of the blocks one workgroup visits (8 slots per thread)
 
-// record a visited block in the workgroup's set; false when the set is full
-__device__ __forceinline__ bool set_insert(int32_t *s_e, unsigned long long *s_k, int32_t e,
-                                           unsigned long long key)
+// Claim a block key in the workgroup's set: the slot, and whether this lane put
+// the key there (its owner: the one lane that probes the hash table for it);
+// -1 when the set is full.  Empty slots hold key 0 (no valid key is 0).
+__device__ __forceinline__ int set_claim(unsigned long long *s_k, unsigned long long key, bool &owner)
 {
-    uint32_t h = ((uint32_t)e * 2654435761u) >> 21;   // 11 bits: kSet slots
+    uint32_t h = (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> 53);   // 11 bits: kSet slots
 #pragma unroll 1
     for (int probe = 0; probe < kSet; probe++, h = (h + 1) & (kSet - 1)) {
-        const int32_t old = atomicCAS(&s_e[h], -1, e);
-        if (old == -1) {
-            s_k[h] = key;
-            return true;
+        const unsigned long long old = atomicCAS(&s_k[h], 0ull, key);
+        if (old == 0ull || old == key) {
+            owner = old == 0ull;
+            return (int)h;
         }
-        if (old == e) return true;
     }
-    return false;
+    owner = false;
+    return -1;
 }
 
 // Expected-depth rectangles of the workgroup's n listed blocks at the frame's
@@ -270,11 +271,25 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
             n[c]--;
             if (n[c] > 0) t[c] = ((float)(b[c] + (st[c] > 0 ? 1 : 0)) - P0[c]) / D[c];
         }
+        // The workgroup's pixels cross the same few blocks: each key is claimed in
+        // the LDS set first, and only its owner probes the hash table and records
+        // the entry in the set (a key that finds the set full is probed, stamped
+        // and listed by its own lane).
+        int slot4[4];
+        uint32_t probe = 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            slot4[q] = -1;
+            if (!valid[q]) continue;
+            bool owner;
+            slot4[q] = set_claim(s_k, pack_key(cx[q], cy[q], cz[q]), owner);
+            if (owner || slot4[q] < 0) probe |= 1u << q;
+        }
         ulonglong2 k2[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             k2[q] = make_ulonglong2(0ull, 0ull);   // no valid key is 0
-            if (valid[q])
+            if (probe & (1u << q))
                 k2[q] = *reinterpret_cast<const ulonglong2 *>(a.h.buckets[hash_index(cx[q], cy[q], cz[q], a.h.mask)].key);
         }
         int32_t e4[4];
@@ -284,7 +299,7 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
             const unsigned long long key = pack_key(cx[q], cy[q], cz[q]);
             const int32_t bi = 2 * (int32_t)hash_index(cx[q], cy[q], cz[q], a.h.mask);
             e4[q] = k2[q].x == key ? bi : k2[q].y == key ? bi + 1 : -1;
-            if (valid[q] && e4[q] < 0) slow |= 1u << q;
+            if ((probe & (1u << q)) && e4[q] < 0) slow |= 1u << q;
         }
         // the full path, from one call site (register selects, no indexed arrays)
         while (slow) {
@@ -300,13 +315,14 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
         }
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            if (!valid[q]) continue;
-            const unsigned long long key = pack_key(cx[q], cy[q], cz[q]);
+            if (!(probe & (1u << q))) continue;
             const int32_t e = e4[q];
-            if (e >= 0 && !set_insert(s_e, s_k, e, key) && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) {
+            if (slot4[q] >= 0) {
+                s_e[slot4[q]] = e;   // -1 (dropped) leaves the slot out of the list
+            } else if (e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) {
                 // the workgroup's set is full: list the block on its own
                 VisRec r;
-                r.key = key;
+                r.key = pack_key(cx[q], cy[q], cz[q]);
                 r.e = e;
                 r.pad = 0;
                 a.list.rec[(int64_t)32 * a.list.cap + atomicAdd(&a.list.cnt[32 * 32], 1)] = r;
@@ -314,6 +330,5 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
         }
     }
 }
-
 
 }  // namespace itm

@@ -254,7 +254,10 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
     int tx, ty;
     if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;   // whole workgroup
 #pragma unroll
-    for (int j = 0; j < kSet / 256; j++) s_e[threadIdx.x + 256 * j] = -1;
+    for (int j = 0; j < kSet / 256; j++) {
+        s_e[threadIdx.x + 256 * j] = -1;
+        s_k[threadIdx.x + 256 * j] = 0ull;
+    }
     __syncthreads();
     // 2. allocation
     {
