@@ -199,8 +199,13 @@ def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True
     sc.enable_colour()
     sc.set_search_range(ranged)
     for f in range(warmup):
+        ev = events and f == warmup - 1   # event pool created before the timed frames
+        if ev:
+            sc.profile(True)
         sc.integrate_colour(depth[f], rgb[f], K, st.T_wc[f])
         sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
+        if ev:
+            sc.profile(False)
     torch.cuda.synchronize()
     s0 = sc.stats()
     sc.profile_read()
@@ -320,8 +325,15 @@ def main():
     ranged = args.search_range == "on"
     sc.set_search_range(ranged)
     for f in range(args.warmup):
+        # the last warm-up frame carries events too: the library creates its event
+        # pool on first use, which must not fall inside the timed frames
+        ev = not args.no_events and f == args.warmup - 1
+        if ev:
+            sc.profile(True)
         sc.integrate(depth[f], K, st.T_wc[f])
         sc.raycast(K, st.T_wc[f], pts, nrm)
+        if ev:
+            sc.profile(False)
     torch.cuda.synchronize()
     s0 = sc.stats()
     sc.profile_read()
