@@ -163,6 +163,7 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
         const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
         float eta[4];
         int pix[4];
+        uchar4 smp[4];
         uint32_t upd = 0, cupd = 0;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -182,6 +183,7 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
             const float y = g.fy * p[1] / p[2] + g.cy;
             if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
             pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
+            if (CLR) smp[j] = a.rgbx[pix[j]];   // with the depth: no dependent read later
             const float d = a.depth[pix[j]];
             if (!(d > 0.0f) || isinf(d)) continue;
             const float e32 = (d - hi[2]) - (lo[2] + dl2);
@@ -209,7 +211,7 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
 #pragma unroll
                 for (int j = 0; j < 4; j++) {
                     if (!(cupd & (1u << j))) continue;
-                    const uchar4 c = colour_step(__builtin_bit_cast(uchar4, c4[j]), a.rgbx[pix[j]], ccap);
+                    const uchar4 c = colour_step(__builtin_bit_cast(uchar4, c4[j]), smp[j], ccap);
                     c4[j] = __builtin_bit_cast(uint32_t, c);
                 }
                 *reinterpret_cast<uint4 *>(a.clr + vbase + li0) = make_uint4(c4[0], c4[1], c4[2], c4[3]);
