@@ -4,7 +4,8 @@
 // One thread per pixel, 16x16 pixel tiles per workgroup so that the lanes of a
 // wave walk neighbouring rays and hit the same buckets.  Per valid pixel:
 // binary64 band-segment end points, binary32 walk over the blocks the segment
-// crosses, and for every block a lookup or a lock-free insertion:
+// crosses, each block's key claimed in the workgroup's LDS set, and for every key
+// the workgroup claims first, a lookup or a lock-free insertion by that one lane:
 //   * bucket slots are claimed with a 64-bit compare-and-swap of the key word, so
 //     two lanes inserting the same block agree on one slot and a key can never
 //     land in a slot once an earlier slot of its bucket holds it;
@@ -17,9 +18,9 @@
 //     once per frame.
 // The paper's stage two (reserve a voxel block) is implicit: every entry owns the
 // voxel block at its own index, so a winning claim is the whole insertion.  For
-// stage three a workgroup gathers the blocks its pixels visited in an LDS set and
-// stamps each with the frame number (an atomic exchange: the first workgroup to
-// stamp a block owns it for the frame).
+// stage three the workgroup stamps each block of its LDS set with the frame
+// number (an atomic exchange: the first workgroup to stamp a block owns it for
+// the frame).
 #pragma once
 
 #include "itm_internal.hpp"

@@ -224,8 +224,9 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
 // Allocation and visible list (itm_alloc.hpp), one thread per pixel:
 //   1. housekeeping, every workgroup its share: the previous frame's claim slots
 //      and, with the search range on, the next frame's bin counts are cleared;
-//   2. each thread walks its pixel's band segment, finds or inserts the blocks,
-//      and records them in the workgroup's LDS set;
+//   2. each thread walks its pixel's band segment and claims the blocks' keys in
+//      the workgroup's LDS set; the lane that claims a key first finds or inserts
+//      the block and records its entry there;
 //   3. every block of the set is stamped with the frame number; the workgroup
 //      that stamps a block first lists it (one atomic per workgroup on one of 32
 //      list stripes), so each visible block is listed exactly once;
