@@ -319,7 +319,10 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
             if (!(probe & (1u << q))) continue;
             const int32_t e = e4[q];
             if (slot4[q] >= 0) {
-                s_e[slot4[q]] = e;   // -1 (dropped) leaves the slot out of the list
+                // stamped at once, while other lanes still probe: the first
+                // workgroup to stamp the block lists it; -1 (dropped, or listed
+                // by another workgroup) leaves the slot out of the list
+                s_e[slot4[q]] = e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now ? e : -1;
             } else if (e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) {
                 // the workgroup's set is full: list the block on its own
                 VisRec r;

@@ -227,9 +227,10 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
 //   2. each thread walks its pixel's band segment and claims the blocks' keys in
 //      the workgroup's LDS set; the lane that claims a key first finds or inserts
 //      the block and records its entry there;
-//   3. every block of the set is stamped with the frame number; the workgroup
-//      that stamps a block first lists it (one atomic per workgroup on one of 32
-//      list stripes), so each visible block is listed exactly once;
+//   3. every block of the set is stamped with the frame number (by the lane that
+//      found it, as soon as it has the entry); the workgroup that stamps a block
+//      first lists it (one atomic per workgroup on one of 32 list stripes), so
+//      each visible block is listed exactly once;
 //   4. with the search range on, the listed blocks' expected-depth rectangles
 //      are binned by image tile.
 __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
@@ -272,12 +273,13 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
         }
     }
     __syncthreads();
-    // 3. the visible list: thread t stamps set slots 8t..8t+7
+    // 3. the visible list: thread t takes set slots 8t..8t+7 (those its workgroup
+    //    stamped first hold their entry)
     uint32_t win = 0;
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         const int32_t e = s_e[8 * threadIdx.x + j];
-        if (e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) win |= 1u << j;
+        if (e >= 0) win |= 1u << j;   // stamped and won in step 2
     }
     const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
     const int c = __builtin_popcount(win);
