@@ -165,32 +165,77 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
         int pix[4];
         uchar4 smp[4];
         uint32_t upd = 0, cupd = 0;
+        if constexpr (!CLR) {
+            // projections first, then the 4 depth reads together: one memory round
+            // instead of four (a read whose value decides a branch is waited for
+            // before the next one is issued)
+            float dep[4];
+            uint32_t seen = 0;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const float fx_ = (float)((li0 & 7) + j);
-            float p[3], dl2 = 0.0f;
+            for (int j = 0; j < 4; j++) {
+                const float fx_ = (float)((li0 & 7) + j);
+                float p[3];
 #pragma unroll
-            for (int c = 0; c < 3; c++) {
-                float t = fx_ * g.g[0][c];
-                t = t + fy_ * g.g[1][c];
-                t = t + fz_ * g.g[2][c];
-                p[c] = hi[c] + (lo[c] + t);
-                if (c == 2) dl2 = t;
+                for (int c = 0; c < 3; c++) {
+                    float t = fx_ * g.g[0][c];
+                    t = t + fy_ * g.g[1][c];
+                    t = t + fz_ * g.g[2][c];
+                    p[c] = hi[c] + (lo[c] + t);
+                }
+                pix[j] = 0;
+                if (p[2] <= 0.0f) continue;
+                const float x = g.fx * p[0] / p[2] + g.cx;
+                const float y = g.fy * p[1] / p[2] + g.cy;
+                if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
+                pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
+                seen |= 1u << j;
             }
-            eta[j] = 0.0f;
-            if (p[2] <= 0.0f) continue;
-            const float x = g.fx * p[0] / p[2] + g.cx;
-            const float y = g.fy * p[1] / p[2] + g.cy;
-            if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
-            pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
-            if (CLR) smp[j] = a.rgbx[pix[j]];   // with the depth: no dependent read later
-            const float d = a.depth[pix[j]];
-            if (!(d > 0.0f) || isinf(d)) continue;
-            const float e32 = (d - hi[2]) - (lo[2] + dl2);
-            if (e32 < -mu) continue;
-            eta[j] = e32;
-            upd |= 1u << j;
-            if (CLR && e32 <= mu) cupd |= 1u << j;   // inside the band: a colour sample
+#pragma unroll
+            for (int j = 0; j < 4; j++) dep[j] = a.depth[pix[j]];   // pixel 0 when unseen: not used
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                eta[j] = 0.0f;
+                if (!(seen & (1u << j))) continue;
+                const float d = dep[j];
+                if (!(d > 0.0f) || isinf(d)) continue;
+                // the voxel's camera-z step, as in its projection (same operations)
+                float dl2 = (float)((li0 & 7) + j) * g.g[0][2];
+                dl2 = dl2 + fy_ * g.g[1][2];
+                dl2 = dl2 + fz_ * g.g[2][2];
+                const float e32 = (d - hi[2]) - (lo[2] + dl2);
+                if (e32 < -mu) continue;
+                eta[j] = e32;
+                upd |= 1u << j;
+            }
+        } else {
+            // the colour form keeps one voxel at a time (its registers are full)
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const float fx_ = (float)((li0 & 7) + j);
+                float p[3], dl2 = 0.0f;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    float t = fx_ * g.g[0][c];
+                    t = t + fy_ * g.g[1][c];
+                    t = t + fz_ * g.g[2][c];
+                    p[c] = hi[c] + (lo[c] + t);
+                    if (c == 2) dl2 = t;
+                }
+                eta[j] = 0.0f;
+                if (p[2] <= 0.0f) continue;
+                const float x = g.fx * p[0] / p[2] + g.cx;
+                const float y = g.fy * p[1] / p[2] + g.cy;
+                if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
+                pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
+                smp[j] = a.rgbx[pix[j]];   // with the depth: no dependent read later
+                const float d = a.depth[pix[j]];
+                if (!(d > 0.0f) || isinf(d)) continue;
+                const float e32 = (d - hi[2]) - (lo[2] + dl2);
+                if (e32 < -mu) continue;
+                eta[j] = e32;
+                upd |= 1u << j;
+                if (e32 <= mu) cupd |= 1u << j;   // inside the band: a colour sample
+            }
         }
         if (upd) {
             Group4<FMT> &v = vg[grp];
