@@ -41,9 +41,9 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 # reports traffic null.
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.9, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga"): {"fetch": 1046.1, "write": 1034.9, "src": "7cf5100249ced759"},
-    ("integrate", "f32", "vga"): {"fetch": 10031.8, "write": 14768.8, "src": "7cf5100249ced759"},
-    ("raycast", "f32", "vga"): {"fetch": 7397.4, "write": 9600.0, "src": "02ec27a622b92ddc"},
+    ("alloc", "f32", "vga"): {"fetch": 1046.1, "write": 1034.8, "src": "b22afe694361acd9"},
+    ("integrate", "f32", "vga"): {"fetch": 10037.7, "write": 14768.9, "src": "b22afe694361acd9"},
+    ("raycast", "f32", "vga"): {"fetch": 7397.5, "write": 9600.0, "src": "02ec27a622b92ddc"},
 }
 
 
