@@ -153,24 +153,17 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
     vg[1].load(a.sdf, a.w, vbase + 4 * lane + 256);
     const int ccap = min((int)g.max_w_f, 255);
     uint32_t n_upd = 0;
+    // depth-only form: both groups' voxels projected first and their 8 depth
+    // reads issued together (one memory round; a read whose value decides a
+    // branch is waited for before the next one is issued)
+    float dep[2][4];
+    uint32_t seen[2] = {0u, 0u};
+    if constexpr (!CLR) {
 #pragma unroll
-    for (int grp = 0; grp < 2; grp++) {
-        const int li0 = 4 * lane + 256 * grp;
-        // the group's 4 colour voxels (16 bytes), loaded here rather than with the
-        // depth voxels: fewer live registers keep 5 waves per SIMD
-        uint4 cgg;
-        if (CLR) cgg = *reinterpret_cast<const uint4 *>(a.clr + vbase + li0);
-        const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
-        float eta[4];
-        int pix[4];
-        uchar4 smp[4];
-        uint32_t upd = 0, cupd = 0;
-        if constexpr (!CLR) {
-            // projections first, then the 4 depth reads together: one memory round
-            // instead of four (a read whose value decides a branch is waited for
-            // before the next one is issued)
-            float dep[4];
-            uint32_t seen = 0;
+        for (int grp = 0; grp < 2; grp++) {
+            const int li0 = 4 * lane + 256 * grp;
+            const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
+            int pix[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const float fx_ = (float)((li0 & 7) + j);
@@ -188,15 +181,30 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
                 const float y = g.fy * p[1] / p[2] + g.cy;
                 if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
                 pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
-                seen |= 1u << j;
+                seen[grp] |= 1u << j;
             }
 #pragma unroll
-            for (int j = 0; j < 4; j++) dep[j] = a.depth[pix[j]];   // pixel 0 when unseen: not used
+            for (int j = 0; j < 4; j++) dep[grp][j] = a.depth[pix[j]];   // pixel 0 when unseen: not used
+        }
+    }
+#pragma unroll
+    for (int grp = 0; grp < 2; grp++) {
+        const int li0 = 4 * lane + 256 * grp;
+        // the group's 4 colour voxels (16 bytes), loaded here rather than with the
+        // depth voxels: fewer live registers keep 5 waves per SIMD
+        uint4 cgg;
+        if (CLR) cgg = *reinterpret_cast<const uint4 *>(a.clr + vbase + li0);
+        const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
+        float eta[4];
+        int pix[4];
+        uchar4 smp[4];
+        uint32_t upd = 0, cupd = 0;
+        if constexpr (!CLR) {
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 eta[j] = 0.0f;
-                if (!(seen & (1u << j))) continue;
-                const float d = dep[j];
+                if (!(seen[grp] & (1u << j))) continue;
+                const float d = dep[grp][j];
                 if (!(d > 0.0f) || isinf(d)) continue;
                 // the voxel's camera-z step, as in its projection (same operations)
                 float dl2 = (float)((li0 & 7) + j) * g.g[0][2];
