@@ -41,9 +41,9 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 # reports traffic null.
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.9, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga"): {"fetch": 1046.1, "write": 1034.8, "src": "b22afe694361acd9"},
-    ("integrate", "f32", "vga"): {"fetch": 10037.7, "write": 14768.9, "src": "b22afe694361acd9"},
-    ("raycast", "f32", "vga"): {"fetch": 7397.5, "write": 9600.0, "src": "02ec27a622b92ddc"},
+    ("alloc", "f32", "vga"): {"fetch": 1046.2, "write": 1034.6, "src": "bbfbd137ed09399d"},
+    ("integrate", "f32", "vga"): {"fetch": 10049.4, "write": 14769.0, "src": "bbfbd137ed09399d"},
+    ("raycast", "f32", "vga"): {"fetch": 7397.7, "write": 9600.0, "src": "02ec27a622b92ddc"},
 }
 
 
