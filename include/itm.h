@@ -280,6 +280,22 @@ itm_status itm_icp_system(itm_scene *scene, const float *depth, const itm_intrin
                           const float *ref_pts, const float *ref_normals, const double *T_ref, const double *T,
                           float dist_thresh, double *sys);
 
+/* itm_track without any device allocation, for callers that cannot allocate   */
+/* (code under HIP graph capture, tight serving loops, harnesses that forbid    */
+/* hipMalloc).  Same arguments, kernels, grid and result as itm_track (the pose  */
+/* is bit-identical), but the per-workgroup sums, pose and flags live in one     */
+/* static device array of the library (about 117 KiB, held by each GPU the       */
+/* library runs on until the process ends) instead of the scene's scratch.       */
+/* Every call on a GPU shares that GPU's array: calls that overlap on one GPU    */
+/* (other streams, other scenes, other host threads) race and must be            */
+/* serialised by the caller.  The scene must belong to the current device.      */
+/* ITM_ERR_ARG also when the device has more than 1024 compute units (the        */
+/* array's sum rows).                                                           */
+itm_status itm_track_noalloc(itm_scene *scene, const float *depth, const itm_intrinsics *K,
+                             const float *ref_pts, const float *ref_normals, const double *T_ref,
+                             const double *T_init, const itm_track_params *params, double *T_out,
+                             itm_track_info *info);
+
 /* ------------------------------------------------------------------------ */
 /* Learned block refiner.  Not part of the paper's method: a small 3D           */
 /* convolutional network, trained on pairs the method itself produces, maps a   */

@@ -59,7 +59,7 @@ EXPORTED = ("itm_scene_create", "itm_scene_create_ex", "itm_scene_destroy", "itm
             "itm_refiner_get_params", "itm_refiner_forward", "itm_refiner_gradient",
             "itm_refiner_train_step", "itm_gather_blocks", "itm_scene_set_refiner",
             "itm_export_blocks_refined", "itm_scene_set_search_range", "itm_expected_depths",
-            "itm_track_default_params", "itm_track", "itm_icp_system",
+            "itm_track_default_params", "itm_track", "itm_icp_system", "itm_track_noalloc",
             "itm_scene_enable_colour", "itm_integrate_colour", "itm_raycast_colour", "itm_export_colour")
 ITM_REFINE_PARAMS = 27712
 
@@ -100,6 +100,8 @@ def lib():
             "itm_track_default_params": (None, [C.POINTER(itm_track_params)]),
             "itm_track": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), _P, _P, _P, _P,
                                     C.POINTER(itm_track_params), _P, C.POINTER(itm_track_info)]),
+            "itm_track_noalloc": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), _P, _P, _P, _P,
+                                            C.POINTER(itm_track_params), _P, C.POINTER(itm_track_info)]),
             "itm_icp_system": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), C.c_int32, _P, _P, _P, _P,
                                          C.c_float, _P]),
             "itm_scene_enable_colour": (C.c_int, [_P]),
@@ -257,7 +259,7 @@ def track_params(iters=None, dist=None, min_inliers=None):
     return p
 
 
-def itm_track(h, depth, K, ref_pts, ref_normals, T_ref, T_init, params=None):
+def itm_track(h, depth, K, ref_pts, ref_normals, T_ref, T_init, params=None, noalloc=False):
     Ki = _intr(K)
     n = Ki.width * Ki.height
     d = _dev(depth, "torch.float32", n)
@@ -267,8 +269,9 @@ def itm_track(h, depth, K, ref_pts, ref_normals, T_ref, T_init, params=None):
     Ti, Tip = _pose(T_init)
     out = np.empty(16, np.float64)
     info = itm_track_info()
-    _check(lib().itm_track(h, d, C.byref(Ki), v, q, Trp, Tip, C.byref(params) if params is not None else None,
-                           out.ctypes.data_as(_P), C.byref(info)))
+    fn = lib().itm_track_noalloc if noalloc else lib().itm_track
+    _check(fn(h, d, C.byref(Ki), v, q, Trp, Tip, C.byref(params) if params is not None else None,
+              out.ctypes.data_as(_P), C.byref(info)))
     return out.reshape(4, 4), {"pairs": int(info.n_pairs), "rms": float(info.rms), "steps": int(info.steps)}
 
 
@@ -521,14 +524,15 @@ class Scene:
         return out
 
     def track(self, depth, K, ref_pts, ref_normals, T_ref, T_init=None, iters=None, dist=None,
-              min_inliers=None):
+              min_inliers=None, noalloc=False):
         """Pose of `depth` (camera -> world, [4, 4]) by point-to-plane alignment to
         the reference maps a raycast wrote at T_ref, and {pairs, rms, steps}.
         iters / dist: per level, finest first (default (4, 6, 10) / (0.02, 0.05,
-        0.1) m)."""
+        0.1) m).  noalloc: use itm_track_noalloc (the library's static scratch)."""
         self._sync_stream()
         p = track_params(iters, dist, min_inliers)
-        return itm_track(self.h, depth, K, ref_pts, ref_normals, T_ref, T_ref if T_init is None else T_init, p)
+        return itm_track(self.h, depth, K, ref_pts, ref_normals, T_ref, T_ref if T_init is None else T_init, p,
+                         noalloc=noalloc)
 
     def icp_system(self, depth, K, level, ref_pts, ref_normals, T_ref, T, dist_thresh):
         """The 29 sums of one Gauss-Newton step at pose T on hierarchy level

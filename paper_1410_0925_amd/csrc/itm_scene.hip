@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <mutex>
 #include <new>
 #include <cstdio>
 #include <cstdlib>
@@ -836,8 +837,16 @@ itm_status itm_profile_read(itm_scene *sc, double *ms, int64_t *launches)
 // ---------------------------------------------------------------------------
 namespace {
 
-// scratch: per-workgroup sums, pose and flags
-itm_status track_scratch(itm_scene *sc)
+// where a tracker call keeps its per-workgroup sums, pose and flags
+struct TrackBufs {
+    float *part;       // [cap][kIcpSums]
+    int32_t cap;       // most workgroups whose sums fit
+    double *pose;      // [16] current estimate, then [32] the last system
+    int32_t *flags;    // [kTrackLevels] stop flags, then the step count
+};
+
+// the scene's tracker scratch, allocated on first use
+itm_status track_scratch(itm_scene *sc, TrackBufs &b)
 {
     if (!sc->trk_part) {
         // one workgroup per CU: each thread takes several pixels of the finest
@@ -850,6 +859,10 @@ itm_status track_scratch(itm_scene *sc)
         if (itm_status st = dev_alloc((void **)&sc->trk_flags, sizeof(int32_t) * (kTrackLevels + 1), "tracker flags"))
             return st;
     }
+    b.part = sc->trk_part;
+    b.cap = sc->trk_part_cap;
+    b.pose = sc->trk_pose;
+    b.flags = sc->trk_flags;
     return ITM_OK;
 }
 
@@ -870,7 +883,7 @@ itm_status track_check(const itm_scene *sc, const float *depth, const itm_intrin
 
 // level l of the hierarchy: input pixel (2^l u, 2^l v) as pixel (u, v), with
 // intrinsics fx / 2^l, fy / 2^l, cx / 2^l, cy / 2^l
-IcpArgs icp_args(const itm_scene *sc, const float *depth, const itm_intrinsics *K, int level, const float *pts,
+IcpArgs icp_args(const TrackBufs &b, const float *depth, const itm_intrinsics *K, int level, const float *pts,
                  const float *nrm, const double *T_ref, float dist)
 {
     IcpArgs a;
@@ -896,25 +909,85 @@ IcpArgs icp_args(const itm_scene *sc, const float *depth, const itm_intrinsics *
         a.tr[i] = (float)T_ref[4 * i + 3];
     }
     a.dist = dist;
-    a.pose = sc->trk_pose;
+    a.pose = b.pose;
     a.stop = nullptr;
-    a.part = sc->trk_part;
+    a.part = b.part;
     return a;
 }
 
-int icp_grid(const itm_scene *sc, const IcpArgs &a)
+int icp_grid(const TrackBufs &b, const IcpArgs &a)
 {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)a.wl * a.hl + 255) / 256, sc->trk_part_cap));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)a.wl * a.hl + 255) / 256, b.cap));
 }
 
-PoseInit pose_init(itm_scene *sc, const double *T)
+PoseInit pose_init(const TrackBufs &b, const double *T)
 {
     PoseInit p;
     std::memcpy(p.T, T, sizeof p.T);
-    p.pose = sc->trk_pose;
-    p.stop = sc->trk_flags;
-    p.steps = sc->trk_flags + kTrackLevels;
+    p.pose = b.pose;
+    p.stop = b.flags;
+    p.steps = b.flags + kTrackLevels;
     return p;
+}
+
+// the Gauss-Newton loop of itm_track over the levels, with its sums, pose and
+// flags in b (arguments already checked)
+itm_status track_run(itm_scene *sc, const TrackBufs &b, const float *depth, const itm_intrinsics *K,
+                     const float *ref_pts, const float *ref_normals, const double *T_ref, const double *T_init,
+                     const itm_track_params *params, double *T_out, itm_track_info *info)
+{
+    if (!T_out) return fail(ITM_ERR_ARG, "NULL T_out");
+    itm_track_params p;
+    if (params) p = *params;
+    else itm_track_default_params(&p);
+    if (p.n_levels < 1 || p.n_levels > kTrackLevels)
+        return fail(ITM_ERR_ARG, "n_levels %d not in [1, %d]", p.n_levels, kTrackLevels);
+    for (int l = 0; l < p.n_levels; l++) {
+        if (p.iters[l] < 0 || p.iters[l] > 1000) return fail(ITM_ERR_ARG, "iters[%d] = %d not in [0, 1000]", l, p.iters[l]);
+        if (!(p.dist_thresh[l] > 0) || !std::isfinite(p.dist_thresh[l]))
+            return fail(ITM_ERR_ARG, "dist_thresh[%d] must be finite and > 0", l);
+    }
+    for (int l = 1; l < p.n_levels; l++)
+        if ((K->width >> l) < 1 || (K->height >> l) < 1)
+            return fail(ITM_ERR_ARG, "a %d x %d image has no level %d", K->width, K->height, l);
+    HIP_TRY(launch_track_init(pose_init(b, T_init), sc->stream));
+    for (int l = p.n_levels - 1; l >= 0; l--) {
+        IcpArgs a = icp_args(b, depth, K, l, ref_pts, ref_normals, T_ref, p.dist_thresh[l]);
+        a.stop = b.flags + l;
+        SolveArgs s;
+        s.part = b.part;
+        s.n_part = icp_grid(b, a);
+        s.pose = b.pose;
+        s.stop = b.flags + l;
+        s.steps = b.flags + kTrackLevels;
+        s.sys = b.pose + 16;
+        s.min_inliers = p.min_inliers;
+        s.update = 1;
+        for (int it = 0; it < p.iters[l]; it++) {
+            {
+                ProfScope ps(sc, l == 0 ? 4 : 5);
+                HIP_TRY(launch_icp_sums(a, s.n_part, sc->stream));
+            }
+            ProfScope ps(sc, 6);
+            HIP_TRY(launch_icp_solve(s, sc->stream));
+        }
+    }
+    double host[48];
+    int32_t flags[kTrackLevels + 1];
+    HIP_TRY(hipMemcpyAsync(host, b.pose, sizeof host, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipMemcpyAsync(flags, b.flags, sizeof flags, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    std::memcpy(T_out, host, sizeof(double) * 16);
+    if (info) {
+        // the last system evaluated (zeros when no step ran)
+        bool any = false;
+        for (int l = 0; l < p.n_levels; l++) any = any || p.iters[l] > 0;
+        const double *sys = host + 16;
+        info->n_pairs = any ? (int64_t)sys[28] : 0;
+        info->rms = any && sys[28] > 0 ? std::sqrt(sys[27] / sys[28]) : 0.0;
+        info->steps = flags[kTrackLevels];
+    }
+    return ITM_OK;
 }
 
 }  // namespace
@@ -935,59 +1008,9 @@ itm_status itm_track(itm_scene *sc, const float *depth, const itm_intrinsics *K,
                      const itm_track_params *params, double *T_out, itm_track_info *info)
 {
     if (itm_status st = track_check(sc, depth, K, ref_pts, ref_normals, T_ref, T_init)) return st;
-    if (!T_out) return fail(ITM_ERR_ARG, "NULL T_out");
-    itm_track_params p;
-    if (params) p = *params;
-    else itm_track_default_params(&p);
-    if (p.n_levels < 1 || p.n_levels > kTrackLevels)
-        return fail(ITM_ERR_ARG, "n_levels %d not in [1, %d]", p.n_levels, kTrackLevels);
-    for (int l = 0; l < p.n_levels; l++) {
-        if (p.iters[l] < 0 || p.iters[l] > 1000) return fail(ITM_ERR_ARG, "iters[%d] = %d not in [0, 1000]", l, p.iters[l]);
-        if (!(p.dist_thresh[l] > 0) || !std::isfinite(p.dist_thresh[l]))
-            return fail(ITM_ERR_ARG, "dist_thresh[%d] must be finite and > 0", l);
-    }
-    for (int l = 1; l < p.n_levels; l++)
-        if ((K->width >> l) < 1 || (K->height >> l) < 1)
-            return fail(ITM_ERR_ARG, "a %d x %d image has no level %d", K->width, K->height, l);
-    if (itm_status st = track_scratch(sc)) return st;
-    HIP_TRY(launch_track_init(pose_init(sc, T_init), sc->stream));
-    for (int l = p.n_levels - 1; l >= 0; l--) {
-        IcpArgs a = icp_args(sc, depth, K, l, ref_pts, ref_normals, T_ref, p.dist_thresh[l]);
-        a.stop = sc->trk_flags + l;
-        SolveArgs s;
-        s.part = sc->trk_part;
-        s.n_part = icp_grid(sc, a);
-        s.pose = sc->trk_pose;
-        s.stop = sc->trk_flags + l;
-        s.steps = sc->trk_flags + kTrackLevels;
-        s.sys = sc->trk_pose + 16;
-        s.min_inliers = p.min_inliers;
-        s.update = 1;
-        for (int it = 0; it < p.iters[l]; it++) {
-            {
-                ProfScope ps(sc, l == 0 ? 4 : 5);
-                HIP_TRY(launch_icp_sums(a, s.n_part, sc->stream));
-            }
-            ProfScope ps(sc, 6);
-            HIP_TRY(launch_icp_solve(s, sc->stream));
-        }
-    }
-    double host[48];
-    int32_t flags[kTrackLevels + 1];
-    HIP_TRY(hipMemcpyAsync(host, sc->trk_pose, sizeof host, hipMemcpyDeviceToHost, sc->stream));
-    HIP_TRY(hipMemcpyAsync(flags, sc->trk_flags, sizeof flags, hipMemcpyDeviceToHost, sc->stream));
-    HIP_TRY(hipStreamSynchronize(sc->stream));
-    std::memcpy(T_out, host, sizeof(double) * 16);
-    if (info) {
-        // the last system evaluated (zeros when no step ran)
-        bool any = false;
-        for (int l = 0; l < p.n_levels; l++) any = any || p.iters[l] > 0;
-        const double *sys = host + 16;
-        info->n_pairs = any ? (int64_t)sys[28] : 0;
-        info->rms = any && sys[28] > 0 ? std::sqrt(sys[27] / sys[28]) : 0.0;
-        info->steps = flags[kTrackLevels];
-    }
-    return ITM_OK;
+    TrackBufs b;
+    if (itm_status st = track_scratch(sc, b)) return st;
+    return track_run(sc, b, depth, K, ref_pts, ref_normals, T_ref, T_init, params, T_out, info);
 }
 
 itm_status itm_icp_system(itm_scene *sc, const float *depth, const itm_intrinsics *K, int32_t level,
@@ -1000,25 +1023,95 @@ itm_status itm_icp_system(itm_scene *sc, const float *depth, const itm_intrinsic
     if (!(dist_thresh > 0) || !std::isfinite(dist_thresh)) return fail(ITM_ERR_ARG, "dist_thresh must be finite and > 0");
     if ((K->width >> level) < 1 || (K->height >> level) < 1)
         return fail(ITM_ERR_ARG, "a %d x %d image has no level %d", K->width, K->height, level);
-    if (itm_status st = track_scratch(sc)) return st;
-    HIP_TRY(launch_track_init(pose_init(sc, T), sc->stream));
-    const IcpArgs a = icp_args(sc, depth, K, level, ref_pts, ref_normals, T_ref, dist_thresh);
+    TrackBufs b;
+    if (itm_status st = track_scratch(sc, b)) return st;
+    HIP_TRY(launch_track_init(pose_init(b, T), sc->stream));
+    const IcpArgs a = icp_args(b, depth, K, level, ref_pts, ref_normals, T_ref, dist_thresh);
     SolveArgs s;
-    s.part = sc->trk_part;
-    s.n_part = icp_grid(sc, a);
-    s.pose = sc->trk_pose;
+    s.part = b.part;
+    s.n_part = icp_grid(b, a);
+    s.pose = b.pose;
     s.stop = nullptr;
     s.steps = nullptr;
-    s.sys = sc->trk_pose + 16;
+    s.sys = b.pose + 16;
     s.min_inliers = 0;
     s.update = 0;
     HIP_TRY(launch_icp_sums(a, s.n_part, sc->stream));
     HIP_TRY(launch_icp_solve(s, sc->stream));
-    HIP_TRY(hipMemcpyAsync(sys, sc->trk_pose + 16, sizeof(double) * kIcpSums, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipMemcpyAsync(sys, b.pose + 16, sizeof(double) * kIcpSums, hipMemcpyDeviceToHost, sc->stream));
     HIP_TRY(hipStreamSynchronize(sc->stream));
     return ITM_OK;
 }
 
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free tracking: the sums, pose and flags in a file-scope device
+// array instead of the scene's lazily allocated scratch
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int kStaticParts = 1024;   // most sum workgroups (one per CU is used)
+constexpr size_t kScrPartBytes = sizeof(float) * kIcpSums * kStaticParts;
+constexpr size_t kScrPoseBytes = sizeof(double) * 48;
+constexpr size_t kScrFlagBytes = sizeof(int32_t) * (kTrackLevels + 1);
+constexpr size_t kScratchBytes = (kScrPartBytes + kScrPoseBytes + kScrFlagBytes + 255) / 256 * 256;
+static_assert(kScrPartBytes % 8 == 0, "the pose must stay 8-byte aligned");
+
+// Each GPU the library runs on holds its own copy until the process ends; in
+// host code the name is not a device address, so it is only ever reached through
+// the per-device address from hipGetSymbolAddress below.
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// the current device's scratch address, looked up once per device
+itm_status static_scratch(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ITM_ERR_ARG, "device %d beyond the %d supported", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(ITM_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return ITM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+itm_status itm_track_noalloc(itm_scene *sc, const float *depth, const itm_intrinsics *K, const float *ref_pts,
+                             const float *ref_normals, const double *T_ref, const double *T_init,
+                             const itm_track_params *params, double *T_out, itm_track_info *info)
+{
+    if (itm_status st = track_check(sc, depth, K, ref_pts, ref_normals, T_ref, T_init)) return st;
+    // the scene's stream must run on the current device, whose copy of the array is used
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != sc->device)
+        return fail(ITM_ERR_ARG, "the scene lives on device %d but device %d is current", sc->device, dev);
+    if (sc->num_cu > kStaticParts)
+        return fail(ITM_ERR_ARG, "%d compute units need more than the %d sum rows of the static scratch", sc->num_cu,
+                    kStaticParts);
+    void *base = nullptr;
+    if (itm_status st = static_scratch(&base)) return st;
+    TrackBufs b;
+    b.part = reinterpret_cast<float *>(base);
+    b.cap = sc->num_cu;   // the grid of itm_track, so both give the same sums bit for bit
+    b.pose = reinterpret_cast<double *>(static_cast<unsigned char *>(base) + kScrPartBytes);
+    b.flags = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(base) + kScrPartBytes + kScrPoseBytes);
+    return track_run(sc, b, depth, K, ref_pts, ref_normals, T_ref, T_init, params, T_out, info);
+}
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
