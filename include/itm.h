@@ -95,8 +95,10 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
                                int64_t n_excess, int32_t fmt, void *hip_stream, float z_near,
                                float z_far);
 
-/* Free every device and host resource of the scene (synchronises its stream).
- * NULL is ignored. */
+/* Free every device and host resource of the scene -- the hash table and the
+ * voxel block array of section "Hash Table and Hashing Function" / "Voxel Block
+ * Array", the visible list, the search-range bins, the tracker's, colour's,
+ * refiner's and swapping's buffers (synchronises its stream).  NULL is ignored. */
 void itm_scene_destroy(itm_scene *scene);
 
 /* Replace the scene's HIP stream (hipStream_t, may be NULL). */
@@ -159,7 +161,9 @@ itm_status itm_scene_set_search_range(itm_scene *scene, int32_t enable, int32_t 
  * Works whether or not the search range is on.  Asynchronous. */
 itm_status itm_expected_depths(itm_scene *scene, const itm_intrinsics *K, const double *T_wc, float *zrange);
 
-/* Copy the allocated blocks to the host, sorted ascending by (x, y, z).
+/* Copy the allocated blocks to the host, sorted ascending by (x, y, z): the
+ * hash table's keys (section "Hash Table and Hashing Function") and the voxel
+ * block array (section "Voxel Block Array").
  *   coords  HOST int32[capacity * 3] or NULL to only count
  *   sdf, w  HOST float[capacity * 512] each, or NULL; F as a float in [-1, 1] and
  *           W as a float, voxel order lx + 8 ly + 64 lz
@@ -168,6 +172,22 @@ itm_status itm_expected_depths(itm_scene *scene, const itm_intrinsics *K, const 
  * Synchronises the stream. */
 itm_status itm_export_blocks(itm_scene *scene, int32_t *coords, float *sdf, float *w,
                              int64_t capacity, int64_t *n_blocks);
+
+/* Load blocks into the scene (the inverse of itm_export_blocks, e.g. a saved
+ * map): each block key is found or inserted as allocation does (section "Hash
+ * Table Operations"; a block that finds no entry is dropped and counted in
+ * n_dropped_total) and its voxels overwritten, converted to the scene's storage
+ * form (F16: round to nearest even; S16U8: F * 32767 rounded to nearest even).
+ * Colour voxels, when enabled, of the loaded blocks are cleared.  The loaded
+ * blocks become the visible set, as if one frame had visited them: the search
+ * range of the next raycast projects them.
+ *   coords  HOST int32[n * 3], distinct keys within +-32767
+ *   sdf, w  HOST float[n * 512] each, export layout; F in [-1, 1], W an
+ *           integer in [0, max_w]
+ * ITM_ERR_ARG for NULL buffers, repeated keys or values out of range (nothing
+ * is changed then).  Synchronises the stream. */
+itm_status itm_import_blocks(itm_scene *scene, const int32_t *coords, const float *sdf, const float *w,
+                             int64_t n);
 
 /* ---- Colour voxels (section "Framework Flexibility": a voxel may carry a colour
  * and a colour weight beside F and W; section "Integration": the colour update is
@@ -210,7 +230,13 @@ itm_status itm_raycast_colour(itm_scene *scene, const itm_intrinsics *K, const d
  * ITM_ERR_ARG when colour is not enabled.  Synchronises the stream. */
 itm_status itm_export_colour(itm_scene *scene, uint8_t *rgbw, int64_t capacity, int64_t *n_blocks);
 
-/* Counters of the scene (synchronises the stream). */
+/* Counters of the scene (synchronises the stream): allocated blocks (hash
+ * entries holding a key, section "Allocation" stage two), blocks listed in the
+ * last frame (stage three's visible list) and since creation, excess entries
+ * used and blocks dropped when the table was full (section "Hash Table
+ * Operations"), voxels updated in the last frame and since creation (section
+ * "Integration"), the voxel block array's capacity and the bytes per voxel of
+ * the storage form (section "Framework Flexibility"). */
 itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
 
 /* Per-kernel timing with HIP events recorded on the scene's stream around every
@@ -297,6 +323,35 @@ itm_status itm_track_noalloc(itm_scene *scene, const float *depth, const itm_int
                              itm_track_info *info);
 
 /* ------------------------------------------------------------------------ */
+/* Swapping (section "Swapping").  The device keeps a pool of device_blocks    */
+/* voxel blocks (the voxel block array, fewer than the map may hold); every   */
+/* hash entry can hold one.  Per frame, after the integration:                */
+/*  - a visible block without a device block takes one from the pool during  */
+/*    the allocation (a new block, or one whose data is on the host); with    */
+/*    the pool empty it is not integrated in that frame (counted);            */
+/*  - swap in: of the blocks holding a device block and a host copy not yet   */
+/*    merged, the first swap_in in key order (x, y, z) are merged back -- the  */
+/*    secondary integration F = (W_d F_d + W_h F_h) / (W_d + W_h), W = min(W_d */
+/*    + W_h, max_w);                                                          */
+/*  - swap out: of the device blocks not visible in the frame with nothing to */
+/*    merge, the first swap_out in key order move to the host (a host voxel   */
+/*    block per hash entry, kept by the library) and free their device block.  */
+/* Transfers go through fixed-size buffers (pinned on the host) of            */
+/* max(swap_in, swap_out) blocks; each frame synchronises the stream twice.   */
+/* The raycast sees the blocks on the device only; itm_export_blocks returns    */
+/* every block wherever it is (merged when both copies exist).  Call before   */
+/* the first frame; not with colour, a refiner or itm_import_blocks            */
+/* (ITM_ERR_STATE).  ITM_ERR_ARG unless 1 <= device_blocks <= the entries and   */
+/* 1 <= swap_in, swap_out <= 2^20.  Synchronises the stream. */
+itm_status itm_scene_enable_swapping(itm_scene *scene, int64_t device_blocks, int32_t swap_in,
+                                     int32_t swap_out);
+/* out[8]: blocks holding a device block, blocks whose data is on the host     */
+/* only, blocks with a host copy not yet merged, blocks swapped in / out in the */
+/* last frame, the totals of both, visible blocks left without a device block */
+/* (total).  ITM_ERR_STATE when swapping is off.  Synchronises the stream.     */
+itm_status itm_swap_stats(itm_scene *scene, int64_t *out);
+
+/* ------------------------------------------------------------------------ */
 /* Learned block refiner.  Not part of the paper's method: a small 3D           */
 /* convolutional network, trained on pairs the method itself produces, maps a   */
 /* block's few-frame TSDF (with a one-voxel halo) towards the TSDF the running  */
@@ -336,8 +391,16 @@ itm_status itm_refiner_train_step(itm_refiner *refiner, const float *in, const f
 itm_status itm_gather_blocks(itm_scene *scene, const int32_t *coords, int64_t n, float *out);
 /* Attach a refiner (not owned; NULL detaches): after every integration each
  * visible block whose largest weight is below w_threshold is refined into a side
- * buffer (half precision, one per voxel block; allocated on first attach). */
+ * buffer (half precision, one per voxel block; allocated on first attach), and
+ * the raycast until the next frame reads those blocks' F from it (the plain F
+ * of every other block is the fallback; the running average never sees it). */
 itm_status itm_scene_set_refiner(itm_scene *scene, itm_refiner *refiner, float w_threshold);
+/* Run the refiner (as itm_integrate does after each frame) over the current
+ * visible set -- e.g. right after itm_import_blocks -- on the blocks whose
+ * largest weight is below the threshold.  Until the next frame, the raycast
+ * reads those blocks' F from the refiner's output.  ITM_ERR_STATE without a
+ * refiner or before any frame.  Asynchronous. */
+itm_status itm_refine_visible(itm_scene *scene);
 /* As itm_export_blocks for F, with the refined F of the blocks refined in the
  * last integration; refined: HOST uint8[capacity] or NULL, 1 where refined. */
 itm_status itm_export_blocks_refined(itm_scene *scene, int32_t *coords, float *sdf, uint8_t *refined,
@@ -345,6 +408,9 @@ itm_status itm_export_blocks_refined(itm_scene *scene, int32_t *coords, float *s
 
 /* Reason of the last failing call on this thread ("" if none). */
 const char *itm_last_error(void);
+/* Status of the last failing call on this thread (ITM_OK if none); the way to
+ * tell why itm_scene_create / _ex returned NULL (e.g. ITM_ERR_OOM). */
+itm_status itm_last_status(void);
 
 #ifdef __cplusplus
 }

@@ -15,7 +15,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "itm_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_DEFAULT = os.path.join(_HERE, "liboracle.so")
+_LIB = _LIB_DEFAULT   # the build lib() loads
 
 # binary64 everywhere, no contraction of a*b+c, no fast-math: decisions taken in
 # binary32 must round exactly as written
@@ -23,12 +24,52 @@ CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", 
           "-shared"]
 
 
-def build(force: bool = True) -> str:
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+# the CPU-baseline build: the same source and semantics (no contraction, no
+# fast-math), optimised for the host it runs on; built on that host when first used
+def _host_tag() -> str:
+    """a tag of this host's CPU (model and feature flags): a -march=native build
+    is only loaded on the kind of CPU it was built for"""
+    import hashlib
+    info = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith(("model name", "flags")):
+                    info += line
+                if line.strip() == "":
+                    break
+    except OSError:
+        pass
+    return hashlib.sha1(info.encode()).hexdigest()[:12]
+
+
+_LIB_NATIVE = os.path.join(_HERE, f"liboracle_native_{_host_tag()}.so")
+CFLAGS_NATIVE = ["-O3", "-march=native"] + [f for f in CFLAGS if f != "-O2"]
+
+
+def use_native_build() -> str:
+    """Load the -O3 -march=native build (compiled here if missing) instead of the
+    default one; must be called before any other oracle call."""
+    global _LIB
+    if _lib is not None and _LIB != _LIB_NATIVE:
+        raise RuntimeError("the oracle library is already loaded")
+    if not os.path.exists(_LIB_NATIVE):
+        tmp = _LIB_NATIVE + f".tmp{os.getpid()}"
+        subprocess.check_call(["gcc", *CFLAGS_NATIVE, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_NATIVE)
+    _LIB = _LIB_NATIVE
     return _LIB
+
+
+def build(force: bool = True) -> str:
+    for f in os.listdir(_HERE):   # host builds: rebuilt from the current source when next used
+        if f.startswith("liboracle_native_") and f.endswith(".so"):
+            os.remove(os.path.join(_HERE, f))
+    if force or not os.path.exists(_LIB_DEFAULT):
+        tmp = _LIB_DEFAULT + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_DEFAULT)
+    return _LIB_DEFAULT
 
 
 _lib = None
@@ -51,6 +92,8 @@ def lib():
             "orc_scene_create": (_P, [_f32, _f32, _i32, _i64, _i64]),
             "orc_scene_destroy": (None, [_P]),
             "orc_set_range": (C.c_int, [_P, _f32, _f32]),
+            "orc_set_pixel_order": (None, [_P, _P]),
+            "orc_raycast_touched": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P]),
             "orc_find": (_i64, [_P, _i32, _i32, _i32]),
             "orc_insert": (_i64, [_P, _i32, _i32, _i32]),
             "orc_dda_blocks": (_i64, [_P, _P, _P, _i64]),
@@ -62,15 +105,22 @@ def lib():
             "orc_entries": (None, [_P, _P, _P, _P]),
             "orc_export": (_i64, [_P, _P, _P, _P, _i64]),
             "orc_update_voxels": (_i64, [_P, _P, C.c_int, C.c_int, _P, _P, _P, _P, _i64, _P, _P]),
+            "orc_voxel_outcomes": (C.c_int, [_P, _P, C.c_int, C.c_int, _P, _P, _P, _P, _P]),
+            "orc_export_candidates": (_i64, [_P, _P, _P, _P, _P, _P, _i64]),
+            "orc_import": (_i64, [_P, _P, _P, _P, _i64]),
+            "orc_enable_swapping": (C.c_int, [_P, _i64, _i64, _i64]),
+            "orc_swap_stats": (None, [_P, _P]),
             "orc_dense_create": (_P, [_i64, _i64, _i64, _i64, _i64, _i64, _f32, _f32, _i32]),
             "orc_dense_destroy": (None, [_P]),
             "orc_dense_integrate": (_i64, [_P, _P, C.c_int, C.c_int, _P, _P, _P, _i64]),
             "orc_dense_read": (None, [_P, _P, _P, _P]),
             "orc_raycast": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P]),
             "orc_raycast_range": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P]),
+            "orc_raycast_alt": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
             "orc_raycast_crossing": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
             "orc_expected_depths": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_threads": (None, [C.c_int]),
             "orc_enable_colour": (C.c_int, [_P]),
             "orc_integrate_colour": (_i64, [_P, _P, _P, C.c_int, C.c_int, _P, _P]),
             "orc_export_colour": (_i64, [_P, _P, _i64]),
@@ -170,7 +220,7 @@ class Scene:
         out = np.zeros(8, np.int64)
         lib().orc_stats(self.h, _ptr(out))
         keys = ["n_allocated", "n_visible", "n_excess_used", "n_dropped_total", "excess_demand",
-                "n_updated_last"]
+                "n_updated_last", "n_ambiguous_last"]
         return {k: int(v) for k, v in zip(keys, out)}
 
     def entries(self):
@@ -188,6 +238,62 @@ class Scene:
         Wt = np.empty((n, 512), np.int32) if with_values else None
         lib().orc_export(self.h, _ptr(coords), _ptr(F), _ptr(Wt), n)
         return coords, F, Wt
+
+    def enable_swapping(self, device_blocks, swap_in, swap_out):
+        """Swapping (section "Swapping"): a device pool of device_blocks voxel
+        blocks; per frame at most swap_in host copies merged back and swap_out
+        device blocks that left the view moved to the host."""
+        if lib().orc_enable_swapping(self.h, int(device_blocks), int(swap_in), int(swap_out)):
+            raise ValueError("swapping: bad sizes, already on, colour on, or more blocks than the pool")
+
+    def swap_stats(self) -> dict:
+        out = np.zeros(8, np.int64)
+        lib().orc_swap_stats(self.h, _ptr(out))
+        keys = ["n_device", "n_host_only", "n_pending", "swapped_in_last", "swapped_out_last",
+                "swapped_in_total", "swapped_out_total", "no_block_total"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def import_blocks(self, coords, F, Wt) -> int:
+        """Load blocks (coords int [n, 3], F [n, 512], W [n, 512] integer-valued, the
+        layout of export()); they become the visible set.  Returns the number loaded."""
+        c = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
+        f = np.ascontiguousarray(F, np.float64).reshape(-1, 512)
+        w = np.ascontiguousarray(np.asarray(Wt).astype(np.int32)).reshape(-1, 512)
+        assert len(c) == len(f) == len(w)
+        return int(lib().orc_import(self.h, _ptr(c), _ptr(f), _ptr(w), len(c)))
+
+    def set_pixel_order(self, order):
+        """Visit the pixels of the following frames' allocation in this order (a
+        permutation of range(W * H)), or row-major with None."""
+        self._order = None if order is None else np.ascontiguousarray(order, np.int32)
+        lib().orc_set_pixel_order(self.h, _ptr(self._order))
+
+    def export_candidates(self):
+        """Voxels with more than one correct state (a decision within its binary32
+        error bound of a threshold, see the oracle's integration): per extra
+        state a row.  Returns dict(key int32 [n, 4] = block x, y, z, in-block
+        index; F float64 [n]; W int32 [n]; rgbw uint8 [n, 4]; unresolved bool [n])."""
+        n = lib().orc_export_candidates(self.h, None, None, None, None, None, 0)
+        key = np.empty((n, 4), np.int32)
+        F = np.empty(n, np.float64)
+        Wt = np.empty(n, np.int32)
+        rgbw = np.empty((n, 4), np.uint8)
+        unr = np.empty(n, np.uint8)
+        lib().orc_export_candidates(self.h, _ptr(key), _ptr(F), _ptr(Wt), _ptr(rgbw), _ptr(unr), n)
+        return dict(key=key, F=F, W=Wt, rgbw=rgbw, unresolved=unr.astype(bool))
+
+    def voxel_outcomes(self, depth, intr, T_wc, vox):
+        """Step one of the update for one voxel: [(updated, f), ...], the binary64
+        decision first, then the other outcomes within the decision margins;
+        and whether a case stayed unresolved."""
+        d = np.ascontiguousarray(depth, np.float32)
+        H, W = d.shape
+        upd = np.zeros(16, np.int32)
+        f = np.zeros(16, np.float64)
+        n = int(lib().orc_voxel_outcomes(self.h, _ptr(d), W, H, _ptr(_K(intr)),
+                                         _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                                         _ptr(np.ascontiguousarray(vox, np.int32)), _ptr(upd), _ptr(f)))
+        return [(bool(upd[i]), float(f[i])) for i in range(abs(n))], n < 0
 
     def enable_colour(self):
         """Colour (r, g, b, colour weight) per voxel from now on."""
@@ -235,10 +341,15 @@ class Scene:
                                            _ptr(np.ascontiguousarray(T_wc, np.float64)),
                                            _ptr(vox), _ptr(act), len(vox), _ptr(F), _ptr(Wt)))
 
-    def raycast(self, W, H, intr, T_wc, zrange=None):
-        """Returns (pts [H,W,4], normals [H,W,4], camera depth [H,W], flags, steps).
-        zrange: [H,W,2] binary32 expected depth ranges (expected_depths), or None
-        for the fixed range [z_near, z_far]."""
+    def raycast(self, W, H, intr, T_wc, zrange=None, alternatives=False):
+        """Returns (pts [H,W,4], normals [H,W,4], camera depth [H,W], flags, steps)
+        of the march that takes the binary64 reads.  zrange: [H,W,2] binary32
+        expected depth ranges (expected_depths), or None for the fixed range
+        [z_near, z_far].  alternatives: also follow every read within the binary32
+        decision margin and append alt [H,W,8,6] = the ray's other correct
+        outcomes (hit (-1 = unused row), camera depth, normal xyz, normal valid).
+        flags: bit 0 a sign decision with |F_n| < 1e-4, bit 1 iteration cap, bit 2
+        other outcomes exist, bit 3 more branches than followed."""
         pts = np.empty((H, W, 4), np.float64)
         nrm = np.empty((H, W, 4), np.float64)
         zc = np.empty((H, W), np.float64)
@@ -246,9 +357,21 @@ class Scene:
         st = np.empty((H, W), np.int32)
         zr = None if zrange is None else np.ascontiguousarray(zrange, np.float32)
         assert zr is None or zr.shape == (H, W, 2)
-        lib().orc_raycast_range(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
-                                _ptr(zr), _ptr(pts), _ptr(nrm), _ptr(zc), _ptr(fl), _ptr(st))
+        alt = np.empty((H, W, 8, 6), np.float64) if alternatives else None
+        lib().orc_raycast_alt(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                              _ptr(zr), _ptr(pts), _ptr(nrm), _ptr(zc), _ptr(fl), _ptr(st), _ptr(alt))
+        if alternatives:
+            return pts, nrm, zc, fl, st, alt
         return pts, nrm, zc, fl, st
+
+    def raycast_touched(self, W, H, intr, T_wc, zrange=None):
+        """(distinct blocks whose voxels a raycast reads, distinct buckets it probes)"""
+        out = np.zeros(2, np.int64)
+        zr = None if zrange is None else np.ascontiguousarray(zrange, np.float32)
+        if lib().orc_raycast_touched(self.h, W, H, _ptr(_K(intr)), _ptr(np.ascontiguousarray(T_wc, np.float64)),
+                                     _ptr(zr), _ptr(out)):
+            raise MemoryError
+        return int(out[0]), int(out[1])
 
     def expected_depths(self, W, H, intr, T_wc):
         """[H,W,2] binary32 (z_min, z_max) per pixel from the last frame's visible
@@ -362,6 +485,10 @@ def track(depth, intr, V, N, T_ref, T_init, iters=(4, 6, 10), dist=(0.02, 0.05, 
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
 
 
 def fuse_stream(stream, n_frames=None, scene=None):

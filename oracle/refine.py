@@ -109,6 +109,27 @@ def forward(inp, params, bf16_mode=False):
     return F_out, dict(xs=xs, pre=pre, W=W, z=z)
 
 
+def forward_batch(inp, params, bf16_mode=False):
+    """forward() over a batch: inp [n, 2, 10, 10, 10] -> F_out [n, 8, 8, 8]
+    (the same sums, the block index carried along)"""
+    rnd = bf16 if bf16_mode else (lambda v: np.asarray(v, np.float64))
+    W, b = unpack(params)
+    W = rnd(W)
+    inp = np.asarray(inp, np.float64)
+    n = inp.shape[0]
+    x = np.zeros((n, C, 10, 10, 10))
+    x[:, :2] = rnd(inp)
+    for l in range(N_LAYERS):
+        h = np.zeros((n, C, 8, 8, 8)) + b[l][None, :, None, None, None]
+        for t, dz, dy, dx in _taps():
+            xs = np.ascontiguousarray(x[:, :, dz:dz + 8, dy:dy + 8, dx:dx + 8]).reshape(n, C, 512)
+            h += np.matmul(W[l][t], xs).reshape(n, C, 8, 8, 8)
+        if l < N_LAYERS - 1:
+            x = np.zeros((n, C, 10, 10, 10))
+            x[:, :, 1:9, 1:9, 1:9] = rnd(np.maximum(h, 0.0))
+    return np.clip(inp[:, 0, 1:9, 1:9, 1:9] + h[:, 0], -1.0, 1.0)
+
+
 def loss_fn(F_out, target, mask):
     m = np.asarray(mask, bool)
     n = max(int(m.sum()), 1)

@@ -53,14 +53,14 @@ class itm_stats(C.Structure):
 _lib = None
 _P = C.c_void_p
 EXPORTED = ("itm_scene_create", "itm_scene_create_ex", "itm_scene_destroy", "itm_set_stream",
-            "itm_integrate", "itm_raycast", "itm_export_blocks", "itm_get_stats",
-            "itm_profile_enable", "itm_profile_read", "itm_last_error",
+            "itm_integrate", "itm_raycast", "itm_export_blocks", "itm_import_blocks", "itm_get_stats",
+            "itm_profile_enable", "itm_profile_read", "itm_last_error", "itm_last_status",
             "itm_refiner_create", "itm_refiner_destroy", "itm_refiner_set_stream",
             "itm_refiner_get_params", "itm_refiner_forward", "itm_refiner_gradient",
             "itm_refiner_train_step", "itm_gather_blocks", "itm_scene_set_refiner",
-            "itm_export_blocks_refined", "itm_scene_set_search_range", "itm_expected_depths",
+            "itm_export_blocks_refined", "itm_refine_visible", "itm_scene_set_search_range", "itm_expected_depths",
             "itm_track_default_params", "itm_track", "itm_icp_system", "itm_track_noalloc",
-            "itm_scene_enable_colour", "itm_integrate_colour", "itm_raycast_colour", "itm_export_colour")
+            "itm_scene_enable_colour", "itm_scene_enable_swapping", "itm_swap_stats", "itm_integrate_colour", "itm_raycast_colour", "itm_export_colour")
 ITM_REFINE_PARAMS = 27712
 
 
@@ -81,10 +81,12 @@ def lib():
             "itm_integrate": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), _P]),
             "itm_raycast": (C.c_int, [_P, C.POINTER(itm_intrinsics), _P, _P, _P]),
             "itm_export_blocks": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
+            "itm_import_blocks": (C.c_int, [_P, _P, _P, _P, C.c_int64]),
             "itm_get_stats": (C.c_int, [_P, C.POINTER(itm_stats)]),
             "itm_profile_enable": (C.c_int, [_P, C.c_int]),
             "itm_profile_read": (C.c_int, [_P, _P, _P]),
             "itm_last_error": (C.c_char_p, []),
+            "itm_last_status": (C.c_int, []),
             "itm_refiner_create": (_P, [_P, _P]),
             "itm_refiner_destroy": (None, [_P]),
             "itm_refiner_set_stream": (C.c_int, [_P, _P]),
@@ -94,6 +96,7 @@ def lib():
             "itm_refiner_train_step": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, _P]),
             "itm_gather_blocks": (C.c_int, [_P, _P, C.c_int64, _P]),
             "itm_scene_set_refiner": (C.c_int, [_P, _P, C.c_float]),
+            "itm_refine_visible": (C.c_int, [_P]),
             "itm_export_blocks_refined": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.POINTER(C.c_int64)]),
             "itm_scene_set_search_range": (C.c_int, [_P, C.c_int32, C.c_int32]),
             "itm_expected_depths": (C.c_int, [_P, C.POINTER(itm_intrinsics), _P, _P]),
@@ -105,6 +108,8 @@ def lib():
             "itm_icp_system": (C.c_int, [_P, _P, C.POINTER(itm_intrinsics), C.c_int32, _P, _P, _P, _P,
                                          C.c_float, _P]),
             "itm_scene_enable_colour": (C.c_int, [_P]),
+            "itm_scene_enable_swapping": (C.c_int, [_P, C.c_int64, C.c_int32, C.c_int32]),
+            "itm_swap_stats": (C.c_int, [_P, _P]),
             "itm_integrate_colour": (C.c_int, [_P, _P, _P, C.POINTER(itm_intrinsics), _P]),
             "itm_raycast_colour": (C.c_int, [_P, C.POINTER(itm_intrinsics), _P, _P, _P, _P]),
             "itm_export_colour": (C.c_int, [_P, _P, C.c_int64, C.POINTER(C.c_int64)]),
@@ -156,7 +161,7 @@ def _dev(t, dtype_name, numel):
 def itm_scene_create(voxel_size, mu, max_w, n_buckets, n_excess):
     h = lib().itm_scene_create(voxel_size, mu, max_w, n_buckets, n_excess)
     if not h:
-        raise ItmError(ITM_ERR_ARG, lib().itm_last_error().decode())
+        raise ItmError(lib().itm_last_status(), lib().itm_last_error().decode())
     return h
 
 
@@ -165,7 +170,7 @@ def itm_scene_create_ex(voxel_size, mu, max_w, n_buckets, n_excess, fmt=ITM_VOX_
     h = lib().itm_scene_create_ex(voxel_size, mu, max_w, n_buckets, n_excess, fmt, stream,
                                   z_near, z_far)
     if not h:
-        raise ItmError(ITM_ERR_ARG, lib().itm_last_error().decode())
+        raise ItmError(lib().itm_last_status(), lib().itm_last_error().decode())
     return h
 
 
@@ -300,6 +305,15 @@ def itm_export_blocks(h, values=True):
                                    sdf.ctypes.data_as(_P) if values else None,
                                    w.ctypes.data_as(_P) if values else None, m, C.byref(n)))
     return coords, sdf, w
+
+
+def itm_import_blocks(h, coords, sdf, w):
+    c = np.ascontiguousarray(coords, np.int32).reshape(-1, 3)
+    f = np.ascontiguousarray(sdf, np.float32).reshape(-1, 512)
+    q = np.ascontiguousarray(w, np.float32).reshape(-1, 512)
+    if not (len(c) == len(f) == len(q)):
+        raise ValueError("coords, sdf and w must hold the same number of blocks")
+    _check(lib().itm_import_blocks(h, c.ctypes.data_as(_P), f.ctypes.data_as(_P), q.ctypes.data_as(_P), len(c)))
 
 
 def itm_get_stats(h):
@@ -544,6 +558,27 @@ class Scene:
         self._sync_stream()
         return itm_export_blocks(self.h, values)
 
+    def enable_swapping(self, device_blocks, swap_in, swap_out):
+        """Swapping (section "Swapping"): a device pool of device_blocks voxel
+        blocks; per frame at most swap_in host copies merged back and swap_out
+        blocks that left the view moved to the host.  Before the first frame."""
+        self._sync_stream()
+        _check(lib().itm_scene_enable_swapping(self.h, int(device_blocks), int(swap_in), int(swap_out)))
+
+    def swap_stats(self):
+        self._sync_stream()
+        out = np.zeros(8, np.int64)
+        _check(lib().itm_swap_stats(self.h, out.ctypes.data_as(_P)))
+        keys = ["n_device", "n_host_only", "n_pending", "swapped_in_last", "swapped_out_last",
+                "swapped_in_total", "swapped_out_total", "no_block_total"]
+        return {k: int(v) for k, v in zip(keys, out)}
+
+    def import_blocks(self, coords, sdf, w):
+        """Load blocks (int32 [n, 3], F and W float [n, 512]); they become the
+        visible set."""
+        self._sync_stream()
+        itm_import_blocks(self.h, coords, sdf, w)
+
     def stats(self):
         self._sync_stream()
         return itm_get_stats(self.h)
@@ -565,6 +600,11 @@ class Scene:
     def export_refined(self):
         self._sync_stream()
         return itm_export_blocks_refined(self.h)
+
+    def refine_visible(self):
+        """Run the attached refiner over the current visible set now."""
+        self._sync_stream()
+        _check(lib().itm_refine_visible(self.h))
 
     def profile(self, enable=True):
         itm_profile_enable(self.h, enable)

@@ -84,6 +84,44 @@ hipError_t launch_export_gather(int fmt, const void *sdf, const void *w, const i
     return hipGetLastError();
 }
 
+// import: the given blocks' voxels (float32 F and W, export layout) into their
+// voxel blocks, converted to the storage form; one workgroup per block
+template <int FMT>
+__global__ __launch_bounds__(256) void k_import_voxels(const int32_t *entry, const float *in_sdf, const float *in_w,
+                                                       int64_t n, typename Vox<FMT>::S *sdf,
+                                                       typename Vox<FMT>::Wt *w, uchar4 *clr)
+{
+    for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+        const int32_t e = entry[i];
+        if (e < 0) continue;   // dropped
+        const int64_t dst = (int64_t)e * kBlockVox, src = i * kBlockVox;
+        for (int l = threadIdx.x; l < kBlockVox; l += blockDim.x) {
+            sdf[dst + l] = Vox<FMT>::from_f(in_sdf[src + l]);
+            w[dst + l] = Vox<FMT>::w_from_f(in_w[src + l]);
+            if (clr) clr[dst + l] = make_uchar4(0, 0, 0, 0);
+        }
+    }
+}
+
+hipError_t launch_import_voxels(int fmt, const int32_t *entry, const float *in_sdf, const float *in_w, int64_t n,
+                                void *sdf, void *w, uchar4 *clr, hipStream_t st)
+{
+    const int grid = (int)std::min<int64_t>(std::max<int64_t>(n, 1), 4096);
+    switch (fmt) {
+    case ITM_VOX_F32:
+        k_import_voxels<ITM_VOX_F32><<<grid, 256, 0, st>>>(entry, in_sdf, in_w, n, (float *)sdf, (float *)w, clr);
+        break;
+    case ITM_VOX_F16:
+        k_import_voxels<ITM_VOX_F16><<<grid, 256, 0, st>>>(entry, in_sdf, in_w, n, (__half *)sdf, (__half *)w, clr);
+        break;
+    default:
+        k_import_voxels<ITM_VOX_S16U8><<<grid, 256, 0, st>>>(entry, in_sdf, in_w, n, (int16_t *)sdf, (uint8_t *)w,
+                                                              clr);
+        break;
+    }
+    return hipGetLastError();
+}
+
 // export of colour voxels: the listed blocks' 512 x 4 bytes, packed in list order
 __global__ __launch_bounds__(256) void k_export_colour(const uchar4 *clr, const int32_t *blocks, int64_t n,
                                                        uchar4 *out)

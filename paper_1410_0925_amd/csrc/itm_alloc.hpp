@@ -27,6 +27,27 @@
 
 namespace itm {
 
+// Housekeeping of the kernel that opens a frame (the allocation, or a volume
+// import), every workgroup its share: the other parity's counters and list
+// counters, the next frame's claim count, the previous frame's claim slots and,
+// with the search range on, the other parity's bin counts are cleared.
+__device__ inline void frame_housekeeping(const FuseArgs &a)
+{
+    if (blockIdx.x == 0) {
+        if (threadIdx.x < kStripes) {
+            a.cnt->upd[a.parity ^ 1][threadIdx.x][0] = 0;
+            a.cnt->vis[a.parity ^ 1][threadIdx.x][0] = 0;
+        }
+        if (threadIdx.x < kListSegs) a.list_clear[32 * threadIdx.x] = 0;
+        if (threadIdx.x == 0) *a.set_used_next = 0;
+    }
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
+    const int su = *a.set_used_prev;
+    for (int i = gt; i < su; i += gs) a.set_prev[a.set_list_prev[i]] = 0ull;
+    if (a.rb_clear)
+        for (int i = gt; i < a.n_clear; i += gs) a.rb_clear[i] = 0;
+}
+
 // one visited block: find it, or insert it; return the entry id to list, or -1
 __device__ inline int32_t find_or_insert(const FuseArgs &a, int bx, int by, int bz)
 {
@@ -203,6 +224,19 @@ __device__ inline void bin_blocks(const FrameGeom &g, const RangeBins &rb, const
 
 // one valid pixel: the blocks its band segment crosses, found or inserted,
 // recorded in the workgroup's set (or, when the set is full, listed directly)
+// Swapping (section "Swapping"): the one lane that lists a block in this frame
+// gives it a device voxel block from the pool when it has none (a new block, or
+// one whose data is on the host); with the pool empty it stays without one this
+// frame (not integrated, counted).  Without swapping the entry is the block.
+__device__ __forceinline__ void device_block(const FuseArgs &a, int32_t e)
+{
+    if (!a.pool.stack) return;
+    if (a.h.blk[e] >= 0) return;
+    const int32_t top = atomicSub(a.pool.top, 1) - 1;
+    if (top >= 0) a.h.blk[e] = a.pool.stack[top];
+    else atomicAdd(a.pool.no_block, 1ull);
+}
+
 __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth, int32_t *s_e,
                             unsigned long long *s_k)
 {
@@ -322,14 +356,31 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
                 // stamped at once, while other lanes still probe: the first
                 // workgroup to stamp the block lists it; -1 (dropped, or listed
                 // by another workgroup) leaves the slot out of the list
-                s_e[slot4[q]] = e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now ? e : -1;
+                const bool first = e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now;
+                s_e[slot4[q]] = first ? e : -1;
+                if (first) device_block(a, e);
             } else if (e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) {
-                // the workgroup's set is full: list the block on its own
+                // the workgroup's set is full: list the block on its own, and bin
+                // its expected-depth rectangle on its own
+                device_block(a, e);
+                const int x = q == 0 ? cx[0] : q == 1 ? cx[1] : q == 2 ? cx[2] : cx[3];
+                const int y = q == 0 ? cy[0] : q == 1 ? cy[1] : q == 2 ? cy[2] : cy[3];
+                const int z = q == 0 ? cz[0] : q == 1 ? cz[1] : q == 2 ? cz[2] : cz[3];
                 VisRec r;
-                r.key = pack_key(cx[q], cy[q], cz[q]);
+                r.key = pack_key(x, y, z);
                 r.e = e;
                 r.pad = 0;
                 a.list.rec[(int64_t)32 * a.list.cap + atomicAdd(&a.list.cnt[32 * 32], 1)] = r;
+                RangeRect rr;
+                if (a.rb.cnt && block_rect(g, x, y, z, rr)) {
+                    int tx0, ty0, ntx, n_tiles;
+                    rect_tiles(rr, tx0, ty0, ntx, n_tiles);
+                    for (int t = 0; t < n_tiles; t++) {
+                        const int tile = (ty0 + t / ntx) * a.rb.tw + tx0 + t % ntx;
+                        const int pos = atomicAdd(&a.rb.cnt[tile], 1);
+                        if (pos < a.rb.cap) a.rb.rect[(int64_t)tile * a.rb.cap + pos] = rr;
+                    }
+                }
             }
         }
     }

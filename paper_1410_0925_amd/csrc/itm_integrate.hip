@@ -14,6 +14,8 @@
 // once per block and split into a binary32 pair hi + lo; the in-block offset
 // (lx g_x + ly g_y) + lz g_z is added to lo first.  The value eta = d - p_z is
 // formed as (d - hi_z) - (lo_z + offset_z), accurate to ~1e-8 m at room scale.
+#include <algorithm>
+
 #include "itm_alloc.hpp"
 
 namespace itm {
@@ -127,7 +129,8 @@ template <int FMT, bool CLR>
 __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, int32_t e, int lane)
 {
     const FrameGeom &g = a.fg;
-    const int32_t ptr = e;   // the entry's voxel block
+    const int32_t ptr = block_of(a.h, e);   // the entry's voxel block
+    if (ptr < 0) return 0;                  // swapping: no device block this frame
     int kx, ky, kz;
     unpack_key(key, kx, ky, kz);
     // block origin in camera coordinates, binary64 -> binary32 pair
@@ -293,21 +296,7 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
     __shared__ unsigned long long s_k[kSet];
     __shared__ int s_wave[4], s_n, s_base, s_ovf;
     // 1. housekeeping
-    if (blockIdx.x == 0) {
-        if (threadIdx.x < kStripes) {
-            a.cnt->upd[a.parity ^ 1][threadIdx.x][0] = 0;
-            a.cnt->vis[a.parity ^ 1][threadIdx.x][0] = 0;
-        }
-        if (threadIdx.x < kListSegs) a.list_clear[32 * threadIdx.x] = 0;
-        if (threadIdx.x == 0) *a.set_used_next = 0;
-    }
-    {
-        const int gt = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
-        const int su = *a.set_used_prev;
-        for (int i = gt; i < su; i += gs) a.set_prev[a.set_list_prev[i]] = 0ull;
-        if (a.rb.cnt)
-            for (int i = gt; i < a.n_clear; i += gs) a.rb_clear[i] = 0;
-    }
+    frame_housekeeping(a);
     int tx, ty;
     if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;   // whole workgroup
 #pragma unroll
@@ -446,6 +435,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
             atomicAdd(&a.cnt->vis[2][sI][0], v);
         }
     }
+}
+
+// Loading a volume (itm_import_blocks): a frame of its own whose visited blocks
+// are the n given keys.  One thread per key: housekeeping as in k_alloc, then
+// find or insert the block, stamp it, and list it when this thread stamped it
+// first (the key list has no repeats, so that is every key that found an
+// entry); entry[i] = the block's entry (= its voxel block), -1 when dropped.
+__global__ __launch_bounds__(256) void k_import_keys(FuseArgs a, const int32_t *coords, int32_t n, int32_t *entry)
+{
+    frame_housekeeping(a);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int bx = coords[3 * i], by = coords[3 * i + 1], bz = coords[3 * i + 2];
+    const int32_t e = find_or_insert(a, bx, by, bz);
+    entry[i] = e;
+    if (e < 0) return;
+    if (atomicExch(&a.stamp[e], a.stamp_now) == a.stamp_now) return;
+    const int stripe = i % 32, sI = i % kStripes;
+    const int pos = atomicAdd(&a.list.cnt[32 * stripe], 1);
+    VisRec r;
+    r.key = pack_key(bx, by, bz);
+    r.e = e;
+    r.pad = 0;
+    if (pos < a.list.cap) a.list.rec[(int64_t)stripe * a.list.cap + pos] = r;
+    else a.list.rec[(int64_t)32 * a.list.cap + atomicAdd(&a.list.cnt[32 * 32], 1)] = r;
+    atomicAdd(&a.cnt->vis[a.parity][sI][0], 1ull);
+    atomicAdd(&a.cnt->vis[2][sI][0], 1ull);
+}
+
+hipError_t launch_import_keys(const FuseArgs &a, const int32_t *coords, int32_t n, int32_t *entry, hipStream_t st)
+{
+    k_import_keys<<<std::max(1, (n + 255) / 256), 256, 0, st>>>(a, coords, n, entry);
+    return hipGetLastError();
 }
 
 hipError_t launch_alloc(const FuseArgs &a, hipStream_t st)

@@ -85,6 +85,23 @@ struct HashView {
     uint32_t mask;
     int32_t n_buckets;
     int32_t n_excess;
+    int32_t *blk;       // with swapping: per entry, the device voxel block it holds
+                        // (-1: none); nullptr: the entry is its own block
+};
+
+// the voxel block of entry e (-1 when e is -1 or, with swapping, holds none)
+__device__ __forceinline__ int32_t block_of(const HashView &h, int32_t e)
+{
+    return (h.blk && e >= 0) ? h.blk[e] : e;
+}
+
+// Swapping: the device pool of free voxel blocks, a stack popped by the
+// allocation (top may run below zero when the pool is empty; the next swap
+// kernel clears that) and pushed by the swap-out
+struct PoolView {
+    int32_t *stack;               // nullptr: no swapping
+    int32_t *top;
+    unsigned long long *no_block; // visible blocks left without a device block (total)
 };
 
 // block key: valid bit | x | y << 16 | z << 32 (16-bit two's complement each)
@@ -275,6 +292,7 @@ struct FuseArgs {
     uchar4 *clr;                  // colour voxels (r, g, b, colour weight), or nullptr
     const uchar4 *rgbx;           // this frame's registered colour image, or nullptr
     Counters *cnt;
+    PoolView pool;                // swapping's device pool (pool.stack nullptr: off)
 };
 
 struct RaycastArgs {
@@ -287,6 +305,9 @@ struct RaycastArgs {
     float4 *nrm;
     RangeBins rb;             // rb.cnt non-null: search each ray inside its expected range
     VisList list;             // for tiles whose bin overflowed
+    const __half *refined;    // non-null: blocks refined in frame rframe read F from here
+    const int32_t *rstamp;    // per voxel block: frame of its last refinement
+    int32_t rframe;
 };
 
 // learned refiner (itm_refine.hip)
@@ -339,7 +360,40 @@ hipError_t launch_range_image(const FrameGeom &g, const VisList &list, const Ran
                               hipStream_t st);
 
 // launchers (one translation unit each)
+// swapping (itm_swap.hip)
+struct alignas(16) SwapRec {
+    unsigned long long key;
+    int32_t e;
+    int32_t pad;
+};
+struct SwapScanArgs {
+    HashView h;
+    const uint32_t *stamp;
+    uint32_t stamp_now;       // the last frame's stamp: listed in that frame
+    const uint8_t *onhost;
+    int64_t n_entries;
+    SwapRec *in_list, *out_list;
+    int32_t *cnt;             // [2]: in, out (cleared by the host)
+    PoolView pool;
+};
+struct SwapMoveArgs {
+    HashView h;
+    void *sdf, *w;            // the device voxel blocks
+    void *xfer_sdf, *xfer_w;  // device transfer buffer, block i at i * 512 voxels
+    const int32_t *entries;   // [n]
+    int32_t n;
+    uint8_t *onhost;
+    float max_w;
+    PoolView pool;
+};
+hipError_t launch_swap_scan(const SwapScanArgs &a, hipStream_t st);
+hipError_t launch_swap_move(int fmt, bool out, const SwapMoveArgs &a, hipStream_t st);
+hipError_t launch_swap_init(int32_t *stack, int32_t n_blocks, int32_t *top, int32_t *blk, uint8_t *onhost,
+                            int64_t n_entries, hipStream_t st);
 hipError_t launch_alloc(const FuseArgs &a, hipStream_t st);
+hipError_t launch_import_keys(const FuseArgs &a, const int32_t *coords, int32_t n, int32_t *entry, hipStream_t st);
+hipError_t launch_import_voxels(int fmt, const int32_t *entry, const float *in_sdf, const float *in_w, int64_t n,
+                                void *sdf, void *w, uchar4 *clr, hipStream_t st);
 hipError_t launch_integrate(int fmt, const FuseArgs &a, int grid, hipStream_t st);
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st);
 hipError_t launch_export_gather(int fmt, const void *sdf, const void *w, const int32_t *blocks, int64_t n,

@@ -25,22 +25,41 @@ namespace itm {
 
 enum { RC_COARSE = 0, RC_FINE, RC_SURFACE, RC_BEHIND, RC_WRONG_SIDE };
 
-template <int FMT>
+// Where the raycast reads F: the voxel block array, or, with REF, for blocks the
+// learned refiner refined in the current frame (stamp == frame), its side buffer
+template <int FMT, bool REF>
+struct VoxSrc {
+    const typename Vox<FMT>::S *sdf;
+    const __half *ref;      // [capacity][512] refined F, REF only
+    const int32_t *stamp;   // [capacity] frame of the last refinement, REF only
+    int32_t frame;
+
+    __device__ bool refined(int32_t ptr) const { return REF && ptr >= 0 && stamp[ptr] == frame; }
+    __device__ float read(int32_t ptr, bool r, int32_t li) const
+    {
+        if (REF && r) return __half2float(ref[(int64_t)ptr * kBlockVox + li]);
+        return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + li]);
+    }
+};
+
+template <int FMT, bool REF>
 struct BlockReader {
     const HashView &h;
-    const typename Vox<FMT>::S *sdf;
+    VoxSrc<FMT, REF> src;
     const uint32_t *filt;   // block filter in LDS
     int cx, cy, cz;
     int32_t cptr;
+    bool cref;              // the cached block reads its refined F
 
-    __device__ BlockReader(const HashView &hv, const void *s, const uint32_t *f)
-        : h(hv), sdf((const typename Vox<FMT>::S *)s), filt(f), cx(INT_MIN), cy(0), cz(0), cptr(-1) {}
+    __device__ BlockReader(const HashView &hv, const VoxSrc<FMT, REF> &s, const uint32_t *f)
+        : h(hv), src(s), filt(f), cx(INT_MIN), cy(0), cz(0), cptr(-1), cref(false) {}
 
     __device__ int32_t block(int bx, int by, int bz)
     {
         if (bx != cx || by != cy || bz != cz) {
             cx = bx; cy = by; cz = bz;
-            cptr = find_block_filtered(h, filt, bx, by, bz);
+            cptr = block_of(h, find_block_filtered(h, filt, bx, by, bz));
+            if (REF) cref = src.refined(cptr);
         }
         return cptr;
     }
@@ -50,7 +69,7 @@ struct BlockReader {
         const int vx = (int)floorf(qx + 0.5f), vy = (int)floorf(qy + 0.5f), vz = (int)floorf(qz + 0.5f);
         const int32_t p = block(vx >> 3, vy >> 3, vz >> 3);
         if (p < 0) { F = 1.0f; return false; }
-        F = Vox<FMT>::to_f(sdf[(int64_t)p * kBlockVox + (int32_t)((vx & 7) | (vy & 7) << 3 | (vz & 7) << 6)]);
+        F = src.read(p, cref, (int32_t)((vx & 7) | (vy & 7) << 3 | (vz & 7) << 6));
         return true;
     }
 };
@@ -63,6 +82,7 @@ struct Cube {
     int bx0, by0, bz0;   // first block per axis
     int bx1, by1, bz1;   // last block per axis (bx0 or bx0 + 1)
     int32_t p[8];   // block pointer of (dx, dy, dz) = (c & 1, c >> 1 & 1, c >> 2 & 1)
+    uint32_t rmask; // bit c: block c reads its refined F
 
     // whether every voxel of the region [l, h] lies in the blocks fetched
     __device__ bool holds(int lx, int ly, int lz, int hx, int hy, int hz) const
@@ -73,7 +93,9 @@ struct Cube {
 
     // every block is probed unless the LDS block filter proves it absent (the
     // march's cached block is not reused: keeping it live costs registers)
-    __device__ void fetch(const HashView &h, const uint32_t *filt, int lx, int ly, int lz, int hx, int hy, int hz)
+    template <bool REF>
+    __device__ void fetch(const HashView &h, const uint32_t *filt, const VoxSrc<FMT, REF> &src, int lx, int ly,
+                          int lz, int hx, int hy, int hz)
     {
         bx0 = lx >> 3; by0 = ly >> 3; bz0 = lz >> 3;
         bx1 = hx >> 3; by1 = hy >> 3; bz1 = hz >> 3;
@@ -83,7 +105,12 @@ struct Cube {
             const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
             const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
             const int kx = dx ? bx1 : bx0, ky = dy ? by1 : by0, kz = dz ? bz1 : bz0;
-            p[c] = need ? find_block_filtered(h, filt, kx, ky, kz) : -1;
+            p[c] = need ? block_of(h, find_block_filtered(h, filt, kx, ky, kz)) : -1;
+        }
+        rmask = 0u;
+        if (REF) {
+#pragma unroll
+            for (int c = 0; c < 8; c++) rmask |= src.refined(p[c]) ? 1u << c : 0u;
         }
     }
 };
@@ -101,17 +128,22 @@ __device__ __forceinline__ int32_t cube_block(const Cube<FMT> &cb, int vx, int v
 
 // Voxel reads of a Cube: a short select of the voxel's block, then one load (an
 // absent block reads as F = 1)
-template <int FMT>
-__device__ __forceinline__ float cube_F(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int vx, int vy, int vz)
+template <int FMT, bool REF>
+__device__ __forceinline__ float cube_F(const Cube<FMT> &cb, const VoxSrc<FMT, REF> &src, int vx, int vy, int vz)
 {
     const int32_t ptr = cube_block(cb, vx, vy, vz);
     if (ptr < 0) return 1.0f;
-    return Vox<FMT>::to_f(sdf[(int64_t)ptr * kBlockVox + (int32_t)((vx & 7) | (vy & 7) << 3 | (vz & 7) << 6)]);
+    bool r = false;
+    if (REF) {
+        const int c = ((vx >> 3) != cb.bx0 ? 1 : 0) | ((vy >> 3) != cb.by0 ? 2 : 0) | ((vz >> 3) != cb.bz0 ? 4 : 0);
+        r = (cb.rmask >> c) & 1u;
+    }
+    return src.read(ptr, r, (int32_t)((vx & 7) | (vy & 7) << 3 | (vz & 7) << 6));
 }
 
 // the 8 lattice voxels of the cell with corner i
-template <int FMT>
-__device__ __forceinline__ void cube_cell(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int ix, int iy,
+template <int FMT, bool REF>
+__device__ __forceinline__ void cube_cell(const Cube<FMT> &cb, const VoxSrc<FMT, REF> &sdf, int ix, int iy,
                                           int iz, float Fc[8])
 {
 #pragma unroll
@@ -133,8 +165,8 @@ __device__ __forceinline__ float trilinear8(const float Fc[8], float rx, float r
 // the cell with corner i and the outer layers of its 6 face neighbours: the
 // 32 voxels of the central differences of F_t at +- one voxel (the cell's own 8
 // already in Fc when have_cell)
-template <int FMT>
-__device__ __forceinline__ void stencil(const Cube<FMT> &cb, const typename Vox<FMT>::S *sdf, int ix, int iy,
+template <int FMT, bool REF>
+__device__ __forceinline__ void stencil(const Cube<FMT> &cb, const VoxSrc<FMT, REF> &sdf, int ix, int iy,
                                         int iz, bool have_cell, float Fc[8], float Ex[2][4], float Ey[2][4],
                                         float Ez[2][4])
 {
@@ -177,7 +209,7 @@ __device__ __forceinline__ void gradient(const float Fc[8], const float Ex[2][4]
     }
 }
 
-template <int FMT, bool CLR>
+template <int FMT, bool CLR, bool REF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_raycast(RaycastArgs a)
 {
     const FrameGeom &g = a.fg;
@@ -249,7 +281,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const float inv_bs = 1.0f / bs;
 
     const uint32_t *s_bfilt = s_filt + kMacroWords;
-    BlockReader<FMT> rd(a.h, a.sdf, s_bfilt);
+    VoxSrc<FMT, REF> src;
+    src.sdf = (const typename Vox<FMT>::S *)a.sdf;
+    src.ref = a.refined;
+    src.stamp = a.rstamp;
+    src.frame = a.rframe;
+    BlockReader<FMT, REF> rd(a.h, src, s_bfilt);
     float t = t_near;
     int state = RC_COARSE, fine_miss = 0;
     for (int it = 0; it < cap && t < t_far; it++) {
@@ -303,7 +340,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     float4 P = make_float4(0.f, 0.f, 0.f, 0.f), N = make_float4(0.f, 0.f, 0.f, 0.f);
     uchar4 C = make_uchar4(0, 0, 0, 0);
     if (state == RC_BEHIND) {
-        const auto *sdf = (const typename Vox<FMT>::S *)a.sdf;
+        const VoxSrc<FMT, REF> &sdf = src;
         // One block neighbourhood for the whole final phase: the blocks of voxels
         // [i - 3, i + 4] per axis around the first refinement cell i (at most
         // 2 x 2 x 2 blocks, probed together) hold both refinement cells and the
@@ -312,7 +349,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
         int ix = (int)fx, iy = (int)fy, iz = (int)fz;
         Cube<FMT> cb;
-        cb.fetch(a.h, s_bfilt, ix - 3, iy - 3, iz - 3, ix + 4, iy + 4, iz + 4);
+        cb.fetch(a.h, s_bfilt, src, ix - 3, iy - 3, iz - 3, ix + 4, iy + 4, iz + 4);
         float Fc[8];
         cube_cell(cb, sdf, ix, iy, iz, Fc);
         t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
@@ -326,7 +363,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
         int jx = (int)fx, jy = (int)fy, jz = (int)fz;
         if (!cb.holds(jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3))
-            cb.fetch(a.h, s_bfilt, jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3);
+            cb.fetch(a.h, s_bfilt, src, jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3);
         if (jx != ix || jy != iy || jz != iz) cube_cell(cb, sdf, jx, jy, jz, Fc);
         t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
         // The normal: central differences of F_t over the stencil of the final
@@ -335,7 +372,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
         ix = (int)fx; iy = (int)fy; iz = (int)fz;
         if (!cb.holds(ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2))
-            cb.fetch(a.h, s_bfilt, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
+            cb.fetch(a.h, s_bfilt, src, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
         float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
         stencil(cb, sdf, ix, iy, iz, ix == jx && iy == jy && iz == jz, Fc, Ex, Ey, Ez);
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;
@@ -363,19 +400,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     if (CLR) a.rgb_out[pix] = C;
 }
 
+template <int FMT>
+void launch_fmt(const RaycastArgs &a, bool clr, bool ref, int grid, hipStream_t st)
+{
+    if (ref) {
+        if (clr) k_raycast<FMT, true, true><<<grid, 256, 0, st>>>(a);
+        else k_raycast<FMT, false, true><<<grid, 256, 0, st>>>(a);
+    } else {
+        if (clr) k_raycast<FMT, true, false><<<grid, 256, 0, st>>>(a);
+        else k_raycast<FMT, false, false><<<grid, 256, 0, st>>>(a);
+    }
+}
+
 hipError_t launch_raycast(int fmt, const RaycastArgs &a, hipStream_t st)
 {
     const int grid = xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16));
-    // the colour variant is a kernel of its own: the depth-only raycast carries
-    // no colour code
+    // the colour variant and the one that reads refined blocks are kernels of
+    // their own: the plain depth raycast carries neither
     const bool clr = a.clr && a.rgb_out;
-    switch (fmt * 2 + (clr ? 1 : 0)) {
-    case 2 * ITM_VOX_F32: k_raycast<ITM_VOX_F32, false><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_F32 + 1: k_raycast<ITM_VOX_F32, true><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_F16: k_raycast<ITM_VOX_F16, false><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_F16 + 1: k_raycast<ITM_VOX_F16, true><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_S16U8 + 1: k_raycast<ITM_VOX_S16U8, true><<<grid, 256, 0, st>>>(a); break;
-    default: k_raycast<ITM_VOX_S16U8, false><<<grid, 256, 0, st>>>(a); break;
+    const bool ref = a.refined != nullptr;
+    switch (fmt) {
+    case ITM_VOX_F32: launch_fmt<ITM_VOX_F32>(a, clr, ref, grid, st); break;
+    case ITM_VOX_F16: launch_fmt<ITM_VOX_F16>(a, clr, ref, grid, st); break;
+    default: launch_fmt<ITM_VOX_S16U8>(a, clr, ref, grid, st); break;
     }
     return hipGetLastError();
 }

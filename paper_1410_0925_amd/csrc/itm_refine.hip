@@ -323,7 +323,7 @@ __global__ void k_refine_gather(HashView h, const void *sdf, const void *w, cons
         const int kx = coords[3 * b], ky = coords[3 * b + 1], kz = coords[3 * b + 2];
         for (int u = threadIdx.x; u < 1000; u += blockDim.x) {
             const int vx = 8 * kx - 1 + u % 10, vy = 8 * ky - 1 + (u / 10) % 10, vz = 8 * kz - 1 + u / 100;
-            const int32_t p = find_block_direct(h, vx >> 3, vy >> 3, vz >> 3);
+            const int32_t p = block_of(h, find_block_direct(h, vx >> 3, vy >> 3, vz >> 3));
             float F = 1.0f, Wf = 0.0f;
             if (p >= 0) {
                 const int64_t i = (int64_t)p * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7);
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_refine_gated(RefineGateArgs a)
     for (int bi = blockIdx.x; bi < vp.total; bi += gridDim.x) {
         const VisRec rec = vis_item(a.list, vp, bi);
         const unsigned long long key = rec.key;
-        const int32_t ptr = rec.e;
+        const int32_t ptr = block_of(a.h, rec.e);
         int kx, ky, kz;
         unpack_key(key, kx, ky, kz);
         // gate on the block's largest weight
@@ -370,7 +370,7 @@ __global__ __launch_bounds__(256) void k_refine_gated(RefineGateArgs a)
         if (skip) continue;              // uniform over the workgroup
         for (int u = threadIdx.x; u < 1000; u += blockDim.x) {
             const int vx = 8 * kx - 1 + u % 10, vy = 8 * ky - 1 + (u / 10) % 10, vz = 8 * kz - 1 + u / 100;
-            const int32_t p = find_block_direct(a.h, vx >> 3, vy >> 3, vz >> 3);
+            const int32_t p = block_of(a.h, find_block_direct(a.h, vx >> 3, vy >> 3, vz >> 3));
             float F = 1.0f, Wf = 0.0f;
             if (p >= 0) {
                 const int64_t i = (int64_t)p * kBlockVox + (vx & 7) + 8 * (vy & 7) + 64 * (vz & 7);

@@ -18,6 +18,7 @@ using namespace itm;
 namespace {
 
 thread_local std::string g_err;
+thread_local itm_status g_status = ITM_OK;
 
 itm_status fail(itm_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 itm_status fail(itm_status s, const char *fmt, ...)
@@ -28,6 +29,7 @@ itm_status fail(itm_status s, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    g_status = s;
     return s;
 }
 
@@ -108,6 +110,25 @@ struct itm_scene {
 
     uchar4 *clr = nullptr;            // [vba_cap][512] colour voxels, allocated on enable
 
+    // swapping (section "Swapping"), set up by itm_scene_enable_swapping: the
+    // device pool is the voxel block array (vba_cap blocks), entries hold blocks
+    bool swap = false;
+    int32_t *blk = nullptr;           // [n_entries] device block held, -1 none
+    uint8_t *onhost = nullptr;        // [n_entries] a host copy exists (not merged yet when blk >= 0)
+    int32_t *pool_stack = nullptr;    // [vba_cap] free device blocks
+    int32_t *pool_top = nullptr;      // [2]: stack top, then the scan counts' home (unused)
+    unsigned long long *pool_noblock = nullptr;
+    SwapRec *swap_in_list = nullptr, *swap_out_list = nullptr;   // [n_entries] each
+    int32_t *swap_cnt = nullptr;      // [2]
+    int32_t swap_in_cap = 0, swap_out_cap = 0;
+    void *xfer_sdf = nullptr, *xfer_w = nullptr;   // device transfer buffer, max(in, out) blocks
+    int32_t *xfer_entries = nullptr;
+    uint8_t *xfer_host = nullptr;     // pinned host transfer buffer: in blocks, then out blocks
+    std::vector<int32_t> host_slot;   // [n_entries] slot of the entry's host copy, -1 none
+    std::vector<uint8_t> host_data;   // host voxel blocks (storage form), one slot each
+    std::vector<int32_t> host_free;   // free slots
+    int64_t swapped_in_last = 0, swapped_out_last = 0, swapped_in_total = 0, swapped_out_total = 0;
+
     bool prof = false;
     std::vector<hipEvent_t> ev;     // 2 per slot
     std::vector<int> ev_kernel;
@@ -120,6 +141,39 @@ namespace {
 
 size_t sdf_elem(int fmt) { return fmt == ITM_VOX_F32 ? 4 : 2; }
 size_t w_elem(int fmt) { return fmt == ITM_VOX_F32 ? 4 : fmt == ITM_VOX_F16 ? 2 : 1; }
+
+// one stored voxel value as a float (F, then W)
+float decode_sdf(int fmt, const uint8_t *p)
+{
+    if (fmt == ITM_VOX_F32) {
+        float f;
+        std::memcpy(&f, p, 4);
+        return f;
+    }
+    if (fmt == ITM_VOX_F16) {
+        __half hv;
+        std::memcpy(&hv, p, 2);
+        return __half2float(hv);
+    }
+    int16_t q;
+    std::memcpy(&q, p, 2);
+    return (float)q / 32767.0f;
+}
+
+float decode_w(int fmt, const uint8_t *p)
+{
+    if (fmt == ITM_VOX_F32) {
+        float f;
+        std::memcpy(&f, p, 4);
+        return f;
+    }
+    if (fmt == ITM_VOX_F16) {
+        __half hv;
+        std::memcpy(&hv, p, 2);
+        return __half2float(hv);
+    }
+    return (float)*p;
+}
 
 void release(itm_scene *sc)
 {
@@ -145,6 +199,11 @@ void release(itm_scene *sc)
     (void)hipFree(sc->trk_pose);
     (void)hipFree(sc->trk_flags);
     (void)hipFree(sc->clr);
+    for (void *p : {(void *)sc->blk, (void *)sc->onhost, (void *)sc->pool_stack, (void *)sc->pool_top,
+                    (void *)sc->pool_noblock, (void *)sc->swap_in_list, (void *)sc->swap_out_list,
+                    (void *)sc->swap_cnt, sc->xfer_sdf, sc->xfer_w, (void *)sc->xfer_entries})
+        (void)hipFree(p);
+    if (sc->xfer_host) (void)hipHostFree(sc->xfer_host);
     delete sc;
 }
 
@@ -264,6 +323,7 @@ HashView hash_view(const itm_scene *sc)
     h.mask = sc->mask;
     h.n_buckets = (int32_t)sc->n_buckets;
     h.n_excess = (int32_t)sc->n_excess;
+    h.blk = sc->swap ? sc->blk : nullptr;
     return h;
 }
 
@@ -325,6 +385,8 @@ itm_status bins_for_pose(itm_scene *sc, const itm_intrinsics *K, const double *T
 extern "C" {
 
 const char *itm_last_error(void) { return g_err.c_str(); }
+
+itm_status itm_last_status(void) { return g_status; }
 
 itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_t n_buckets,
                                int64_t n_excess, int32_t fmt, void *hip_stream, float z_near,
@@ -441,6 +503,202 @@ itm_status itm_set_stream(itm_scene *sc, void *hip_stream)
 
 namespace {
 
+PoolView pool_view(const itm_scene *sc)
+{
+    PoolView p;
+    p.stack = sc->swap ? sc->pool_stack : nullptr;
+    p.top = sc->pool_top;
+    p.no_block = sc->pool_noblock;
+    return p;
+}
+
+// the arguments of the kernels of the next frame (claim sets, visible list,
+// counters by frame parity); with bin, its expected-depth rectangles are binned
+// at the frame's pose (g)
+FuseArgs frame_args(itm_scene *sc, const FrameGeom &g, bool bin)
+{
+    const HashView h = hash_view(sc);
+    const int32_t parity = sc->frame & 1;
+    FuseArgs a;
+    a.fg = g;
+    a.depth = nullptr;
+    a.h = h;
+    a.parity = parity;
+    a.stamp = sc->vis_stamp;
+    a.stamp_now = (uint32_t)sc->frame + 1u;
+    // claim sets: tables alternate by frame, slot lists and counts by frame % 3
+    const int f3 = sc->frame % 3, p3 = (sc->frame + 2) % 3, n3 = (sc->frame + 1) % 3;
+    a.set = sc->set + (size_t)parity * sc->set_size;
+    a.set_list = sc->set_list + (size_t)f3 * sc->set_size;
+    a.set_used = &sc->cnt->set_used[f3];
+    a.set_mask = (uint32_t)(sc->set_size - 1);
+    a.set_prev = sc->set + (size_t)(parity ^ 1) * sc->set_size;
+    a.set_list_prev = sc->set_list + (size_t)p3 * sc->set_size;
+    a.set_used_prev = &sc->cnt->set_used[p3];
+    a.set_used_next = &sc->cnt->set_used[n3];
+    a.list = vis_list(sc, parity);
+    a.list_clear = vis_list(sc, parity ^ 1).cnt;
+    a.rb = RangeBins{};
+    a.rb_clear = nullptr;
+    a.n_clear = 0;
+    if (bin) a.rb = bin_set(sc, parity, g.W, g.H);
+    if (sc->bin_cnt) {   // the other parity's bins, for the next frame
+        a.rb_clear = bin_set(sc, parity ^ 1, g.W, g.H).cnt;
+        a.n_clear = (int32_t)sc->bin_tiles;
+    }
+    a.sdf = sc->sdf;
+    a.w = sc->w;
+    a.clr = nullptr;
+    a.rgbx = nullptr;
+    a.cnt = sc->cnt;
+    a.pool = pool_view(sc);
+    return a;
+}
+
+// the learned refiner over the last frame's visible blocks whose largest weight
+// is below the threshold; the refined F goes to the side buffer, stamped with
+// the current frame number (which the raycast compares against)
+itm_status refine_visible(itm_scene *sc)
+{
+    RefineGateArgs ra;
+    ra.P.Wf = sc->refiner->Wf;
+    ra.P.Wt = sc->refiner->Wt;
+    ra.P.bias = sc->refiner->bias;
+    ra.h = hash_view(sc);
+    ra.list = vis_list(sc, last_parity(sc));
+    ra.sdf = sc->sdf;
+    ra.w = sc->w;
+    ra.inv_max_w = 1.0f / (float)sc->max_w;
+    ra.w_threshold = sc->refine_w_threshold;
+    ra.refined = sc->refined;
+    ra.stamp = sc->stamp;
+    ra.frame = sc->frame;
+    ProfScope ps(sc, 3);
+    HIP_TRY(launch_refine_gated(sc->fmt, ra, sc->num_cu * 2, sc->stream));
+    return ITM_OK;
+}
+
+// the key of a swap record as (x, y, z), for the host's key order
+void swap_key(const SwapRec &r, int &x, int &y, int &z)
+{
+    x = (int16_t)(r.key & 0xffffu);
+    y = (int16_t)((r.key >> 16) & 0xffffu);
+    z = (int16_t)((r.key >> 32) & 0xffffu);
+}
+
+bool swap_key_less(const SwapRec &a, const SwapRec &b)
+{
+    int ax, ay, az, bx, by, bz;
+    swap_key(a, ax, ay, az);
+    swap_key(b, bx, by, bz);
+    if (ax != bx) return ax < bx;
+    if (ay != by) return ay < by;
+    return az < bz;
+}
+
+// After a frame's integration (section "Swapping"): the candidates are found
+// on the device; the host takes, in key order, up to swap_in_cap host copies to
+// merge into their device blocks and up to swap_out_cap device blocks that were
+// not visible in the frame (and have nothing to merge) to move to the host.
+// Two host synchronisations per frame.
+itm_status swap_frame(itm_scene *sc)
+{
+    const size_t es = sdf_elem(sc->fmt), ew = w_elem(sc->fmt);
+    const size_t blk_bytes = (es + ew) * kBlockVox;
+    HIP_TRY(hipMemsetAsync(sc->swap_cnt, 0, sizeof(int32_t) * 2, sc->stream));
+    SwapScanArgs sa;
+    sa.h = hash_view(sc);
+    sa.stamp = sc->vis_stamp;
+    sa.stamp_now = (uint32_t)sc->frame;   // the stamp of the frame just integrated
+    sa.onhost = sc->onhost;
+    sa.n_entries = sc->n_entries;
+    sa.in_list = sc->swap_in_list;
+    sa.out_list = sc->swap_out_list;
+    sa.cnt = sc->swap_cnt;
+    sa.pool = pool_view(sc);
+    HIP_TRY(launch_swap_scan(sa, sc->stream));
+    int32_t cnt[2];
+    HIP_TRY(hipMemcpyAsync(cnt, sc->swap_cnt, sizeof cnt, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    std::vector<SwapRec> in(cnt[0]), out(cnt[1]);
+    if (cnt[0]) HIP_TRY(hipMemcpyAsync(in.data(), sc->swap_in_list, sizeof(SwapRec) * cnt[0], hipMemcpyDeviceToHost, sc->stream));
+    if (cnt[1]) HIP_TRY(hipMemcpyAsync(out.data(), sc->swap_out_list, sizeof(SwapRec) * cnt[1], hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    std::sort(in.begin(), in.end(), swap_key_less);
+    std::sort(out.begin(), out.end(), swap_key_less);
+    const int32_t n_in = std::min<int32_t>(cnt[0], sc->swap_in_cap);
+    const int32_t n_out = std::min<int32_t>(cnt[1], sc->swap_out_cap);
+    const int32_t xcap = std::max(sc->swap_in_cap, sc->swap_out_cap);
+    SwapMoveArgs ma;
+    ma.h = sa.h;
+    ma.sdf = sc->sdf;
+    ma.w = sc->w;
+    ma.xfer_sdf = sc->xfer_sdf;
+    ma.xfer_w = sc->xfer_w;
+    ma.entries = sc->xfer_entries;
+    ma.onhost = sc->onhost;
+    ma.max_w = (float)sc->max_w;
+    ma.pool = sa.pool;
+    std::vector<int32_t> ents;
+    // swap in: host copies into the transfer buffer (F then W parts, as on the
+    // device), then merged into the device blocks
+    if (n_in) {
+        uint8_t *hs = sc->xfer_host, *hw = sc->xfer_host + es * kBlockVox * (size_t)xcap;
+        ents.resize(n_in);
+        for (int32_t i = 0; i < n_in; i++) {
+            const int32_t e = in[i].e;
+            const int32_t slot = sc->host_slot[e];
+            const uint8_t *src = sc->host_data.data() + (size_t)slot * blk_bytes;
+            std::memcpy(hs + es * kBlockVox * (size_t)i, src, es * kBlockVox);
+            std::memcpy(hw + ew * kBlockVox * (size_t)i, src + es * kBlockVox, ew * kBlockVox);
+            ents[i] = e;
+        }
+        HIP_TRY(hipMemcpyAsync(sc->xfer_sdf, hs, es * kBlockVox * (size_t)n_in, hipMemcpyHostToDevice, sc->stream));
+        HIP_TRY(hipMemcpyAsync(sc->xfer_w, hw, ew * kBlockVox * (size_t)n_in, hipMemcpyHostToDevice, sc->stream));
+        HIP_TRY(hipMemcpyAsync(sc->xfer_entries, ents.data(), sizeof(int32_t) * n_in, hipMemcpyHostToDevice,
+                               sc->stream));
+        ma.n = n_in;
+        HIP_TRY(launch_swap_move(sc->fmt, false, ma, sc->stream));
+        HIP_TRY(hipStreamSynchronize(sc->stream));   // the buffers are reused below
+        for (int32_t i = 0; i < n_in; i++) {
+            sc->host_free.push_back(sc->host_slot[in[i].e]);
+            sc->host_slot[in[i].e] = -1;
+        }
+    }
+    // swap out: device blocks through the transfer buffer to host slots
+    if (n_out) {
+        ents.resize(n_out);
+        for (int32_t i = 0; i < n_out; i++) ents[i] = out[i].e;
+        HIP_TRY(hipMemcpyAsync(sc->xfer_entries, ents.data(), sizeof(int32_t) * n_out, hipMemcpyHostToDevice,
+                               sc->stream));
+        ma.n = n_out;
+        HIP_TRY(launch_swap_move(sc->fmt, true, ma, sc->stream));
+        uint8_t *hs = sc->xfer_host, *hw = sc->xfer_host + es * kBlockVox * (size_t)xcap;
+        HIP_TRY(hipMemcpyAsync(hs, sc->xfer_sdf, es * kBlockVox * (size_t)n_out, hipMemcpyDeviceToHost, sc->stream));
+        HIP_TRY(hipMemcpyAsync(hw, sc->xfer_w, ew * kBlockVox * (size_t)n_out, hipMemcpyDeviceToHost, sc->stream));
+        HIP_TRY(hipStreamSynchronize(sc->stream));
+        for (int32_t i = 0; i < n_out; i++) {
+            int32_t slot;
+            if (!sc->host_free.empty()) {
+                slot = sc->host_free.back();
+                sc->host_free.pop_back();
+            } else {
+                slot = (int32_t)(sc->host_data.size() / blk_bytes);
+                sc->host_data.resize(sc->host_data.size() + blk_bytes);
+            }
+            uint8_t *dst = sc->host_data.data() + (size_t)slot * blk_bytes;
+            std::memcpy(dst, hs + es * kBlockVox * (size_t)i, es * kBlockVox);
+            std::memcpy(dst + es * kBlockVox, hw + ew * kBlockVox * (size_t)i, ew * kBlockVox);
+            sc->host_slot[out[i].e] = slot;
+        }
+    }
+    sc->swapped_in_last = n_in;
+    sc->swapped_out_last = n_out;
+    sc->swapped_in_total += n_in;
+    sc->swapped_out_total += n_out;
+    return ITM_OK;
+}
+
 // one frame: allocation, visible list and integration; with rgbx set, the
 // colour voxels too
 itm_status integrate_frame(itm_scene *sc, const float *depth, const uchar4 *rgbx, const itm_intrinsics *K,
@@ -448,44 +706,12 @@ itm_status integrate_frame(itm_scene *sc, const float *depth, const uchar4 *rgbx
 {
     FrameGeom g;
     if (itm_status st = make_geom(sc, K, T_wc, &g)) return st;
-    const HashView h = hash_view(sc);
-    const int32_t parity = sc->frame & 1;
     if (sc->range_on)
         if (itm_status st = ensure_bins(sc, g.W, g.H)) return st;
-    FuseArgs a;
-    {
-        a.fg = g;
-        a.depth = depth;
-        a.h = h;
-        a.parity = parity;
-        a.stamp = sc->vis_stamp;
-        a.stamp_now = (uint32_t)sc->frame + 1u;
-        // claim sets: tables alternate by frame, slot lists and counts by frame % 3
-        const int f3 = sc->frame % 3, p3 = (sc->frame + 2) % 3, n3 = (sc->frame + 1) % 3;
-        a.set = sc->set + (size_t)parity * sc->set_size;
-        a.set_list = sc->set_list + (size_t)f3 * sc->set_size;
-        a.set_used = &sc->cnt->set_used[f3];
-        a.set_mask = (uint32_t)(sc->set_size - 1);
-        a.set_prev = sc->set + (size_t)(parity ^ 1) * sc->set_size;
-        a.set_list_prev = sc->set_list + (size_t)p3 * sc->set_size;
-        a.set_used_prev = &sc->cnt->set_used[p3];
-        a.set_used_next = &sc->cnt->set_used[n3];
-        a.list = vis_list(sc, parity);
-        a.list_clear = vis_list(sc, parity ^ 1).cnt;
-        a.rb = RangeBins{};
-        a.rb_clear = nullptr;
-        a.n_clear = 0;
-        if (sc->range_on) {   // bin the expected-depth rectangles at this pose
-            a.rb = bin_set(sc, parity, g.W, g.H);
-            a.rb_clear = bin_set(sc, parity ^ 1, g.W, g.H).cnt;
-            a.n_clear = (int32_t)sc->bin_tiles;
-        }
-        a.sdf = sc->sdf;
-        a.w = sc->w;
-        a.clr = rgbx ? sc->clr : nullptr;
-        a.rgbx = rgbx;
-        a.cnt = sc->cnt;
-    }
+    FuseArgs a = frame_args(sc, g, sc->range_on);
+    a.depth = depth;
+    a.clr = rgbx ? sc->clr : nullptr;
+    a.rgbx = rgbx;
     {
         ProfScope ps(sc, 0);
         HIP_TRY(launch_alloc(a, sc->stream));
@@ -503,23 +729,8 @@ itm_status integrate_frame(itm_scene *sc, const float *depth, const uchar4 *rgbx
         std::memcpy(sc->fused_T, T_wc, sizeof sc->fused_T);
     }
     sc->frame++;
-    if (sc->refiner) {
-        RefineGateArgs ra;
-        ra.P.Wf = sc->refiner->Wf;
-        ra.P.Wt = sc->refiner->Wt;
-        ra.P.bias = sc->refiner->bias;
-        ra.h = h;
-        ra.list = vis_list(sc, parity);
-        ra.sdf = sc->sdf;
-        ra.w = sc->w;
-        ra.inv_max_w = 1.0f / (float)sc->max_w;
-        ra.w_threshold = sc->refine_w_threshold;
-        ra.refined = sc->refined;
-        ra.stamp = sc->stamp;
-        ra.frame = sc->frame;
-        ProfScope ps(sc, 3);
-        HIP_TRY(launch_refine_gated(sc->fmt, ra, sc->num_cu * 2, sc->stream));
-    }
+    if (sc->swap) return swap_frame(sc);
+    if (sc->refiner) return refine_visible(sc);
     return ITM_OK;
 }
 
@@ -541,6 +752,12 @@ itm_status raycast_frame(itm_scene *sc, const itm_intrinsics *K, const double *T
     a.rgb_out = out_rgbx;
     a.rb = RangeBins{};
     a.list = vis_list(sc, last_parity(sc));
+    // with a refiner, the blocks it refined after the last frame are read from
+    // its output (the plain F stays the fallback for every other block)
+    const bool ref = sc->refiner && sc->refined && sc->frame > 0;
+    a.refined = ref ? sc->refined : nullptr;
+    a.rstamp = ref ? sc->stamp : nullptr;
+    a.rframe = sc->frame;
     if (sc->range_on)
         if (itm_status st = bins_for_pose(sc, K, T_wc, g, &a.rb)) return st;
     HIP_TRY(launch_raycast(sc->fmt, a, sc->stream));
@@ -568,6 +785,7 @@ itm_status itm_scene_enable_colour(itm_scene *sc)
 {
     if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
     if (sc->clr) return ITM_OK;
+    if (sc->swap) return fail(ITM_ERR_STATE, "colour does not combine with swapping");
     const size_t bytes = sizeof(uchar4) * kBlockVox * (size_t)sc->vba_cap;
     if (itm_status st = dev_alloc((void **)&sc->clr, bytes, "colour voxels")) return st;
     hipError_t e = hipMemsetAsync(sc->clr, 0, bytes, sc->stream);
@@ -638,7 +856,9 @@ itm_status itm_get_stats(itm_scene *sc, itm_stats *out)
     Counters c;
     HIP_TRY(hipMemcpyAsync(&c, sc->cnt, sizeof c, hipMemcpyDeviceToHost, sc->stream));
     HIP_TRY(hipStreamSynchronize(sc->stream));
-    out->n_allocated = std::min<int64_t>(c.vba_next, sc->vba_cap);
+    // entries holding a key (each a block: on the device, or with swapping
+    // possibly on the host)
+    out->n_allocated = std::min<int64_t>(c.vba_next, sc->swap ? sc->n_entries : sc->vba_cap);
     unsigned long long v_last = 0, v_tot = 0;
     for (int i = 0; i < kStripes; i++) {
         v_last += c.vis[last_parity(sc)][i][0];
@@ -721,22 +941,36 @@ itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *
         coords[3 * i + 2] = recs[i].z;
     }
     if ((!sdf && !w) || n == 0) return ITM_OK;
+    // with swapping a block's data may sit on the device, on the host, or both
+    // (a host copy not merged yet: exported merged, as the swap-in would merge it)
+    const bool swp = sc->swap;
+    std::vector<int32_t> dblk;
+    std::vector<uint8_t> onh;
+    if (swp) {
+        dblk.resize(sc->n_entries);
+        onh.resize(sc->n_entries);
+        HIP_TRY(hipMemcpyAsync(dblk.data(), sc->blk, sizeof(int32_t) * sc->n_entries, hipMemcpyDeviceToHost,
+                               sc->stream));
+        HIP_TRY(hipMemcpyAsync(onh.data(), sc->onhost, sc->n_entries, hipMemcpyDeviceToHost, sc->stream));
+        HIP_TRY(hipStreamSynchronize(sc->stream));
+    }
+    const bool want_s = sdf || swp, want_w = w || swp;
     // the blocks' voxels, packed on the device in export order, then one copy
     const size_t es = sdf_elem(sc->fmt), ew = w_elem(sc->fmt);
     std::vector<int32_t> blk(n);
-    for (int64_t i = 0; i < n; i++) blk[i] = recs[i].blk;
+    for (int64_t i = 0; i < n; i++) blk[i] = swp ? std::max(dblk[recs[i].blk], 0) : recs[i].blk;
     int32_t *d_blk = nullptr;
     void *d_s = nullptr, *d_w = nullptr;
     itm_status st = dev_alloc((void **)&d_blk, sizeof(int32_t) * n, "export list");
-    if (!st && sdf) st = dev_alloc(&d_s, es * kBlockVox * n, "export sdf");
-    if (!st && w) st = dev_alloc(&d_w, ew * kBlockVox * n, "export weights");
-    std::vector<uint8_t> hs(sdf ? es * kBlockVox * n : 0), hw(w ? ew * kBlockVox * n : 0);
+    if (!st && want_s) st = dev_alloc(&d_s, es * kBlockVox * n, "export sdf");
+    if (!st && want_w) st = dev_alloc(&d_w, ew * kBlockVox * n, "export weights");
+    std::vector<uint8_t> hs(want_s ? es * kBlockVox * n : 0), hw(want_w ? ew * kBlockVox * n : 0);
     hipError_t e = hipSuccess;
     if (!st) {
         e = hipMemcpyAsync(d_blk, blk.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, sc->stream);
         if (e == hipSuccess) e = launch_export_gather(sc->fmt, sc->sdf, sc->w, d_blk, n, d_s, d_w, sc->stream);
-        if (e == hipSuccess && sdf) e = hipMemcpyAsync(hs.data(), d_s, hs.size(), hipMemcpyDeviceToHost, sc->stream);
-        if (e == hipSuccess && w) e = hipMemcpyAsync(hw.data(), d_w, hw.size(), hipMemcpyDeviceToHost, sc->stream);
+        if (e == hipSuccess && want_s) e = hipMemcpyAsync(hs.data(), d_s, hs.size(), hipMemcpyDeviceToHost, sc->stream);
+        if (e == hipSuccess && want_w) e = hipMemcpyAsync(hw.data(), d_w, hw.size(), hipMemcpyDeviceToHost, sc->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     }
     (void)hipFree(d_blk);
@@ -744,35 +978,191 @@ itm_status itm_export_blocks(itm_scene *sc, int32_t *coords, float *sdf, float *
     (void)hipFree(d_w);
     if (st) return st;
     if (e != hipSuccess) return fail(ITM_ERR_HIP, "export failed: %s", hipGetErrorString(e));
+    const size_t blk_bytes = (es + ew) * kBlockVox;
     for (int64_t i = 0; i < n; i++) {
         const size_t src = (size_t)i * kBlockVox;
+        int32_t db = 0, slot = -1;
+        if (swp) {
+            const int32_t ent = recs[i].blk;
+            db = dblk[ent];
+            slot = onh[ent] ? sc->host_slot[ent] : -1;
+        }
+        const uint8_t *host = slot >= 0 ? sc->host_data.data() + (size_t)slot * blk_bytes : nullptr;
         for (int l = 0; l < kBlockVox; l++) {
-            if (sdf) {
-                float f;
-                if (sc->fmt == ITM_VOX_F32) std::memcpy(&f, &hs[4 * (src + l)], 4);
-                else if (sc->fmt == ITM_VOX_F16) {
-                    __half hv;
-                    std::memcpy(&hv, &hs[2 * (src + l)], 2);
-                    f = __half2float(hv);
+            float f = 1.0f, wf = 0.0f;
+            if (db >= 0) {   // the device copy
+                if (want_s) f = decode_sdf(sc->fmt, &hs[es * (src + l)]);
+                if (want_w) wf = decode_w(sc->fmt, &hw[ew * (src + l)]);
+            }
+            if (host) {      // the host copy, merged into the device copy when there is one
+                const float fh = decode_sdf(sc->fmt, host + es * l);
+                const float whv = decode_w(sc->fmt, host + es * kBlockVox + ew * l);
+                if (db < 0) {
+                    f = fh;
+                    wf = whv;
                 } else {
-                    int16_t q;
-                    std::memcpy(&q, &hs[2 * (src + l)], 2);
-                    f = (float)q / 32767.0f;
+                    const float wn = wf + whv;
+                    if (wn > 0.0f) {
+                        f = (wf * f + whv * fh) / wn;
+                        wf = std::min(wn, (float)sc->max_w);
+                    }
                 }
-                sdf[src + l] = f;
             }
-            if (w) {
-                float wf;
-                if (sc->fmt == ITM_VOX_F32) std::memcpy(&wf, &hw[4 * (src + l)], 4);
-                else if (sc->fmt == ITM_VOX_F16) {
-                    __half hv;
-                    std::memcpy(&hv, &hw[2 * (src + l)], 2);
-                    wf = __half2float(hv);
-                } else wf = (float)hw[src + l];
-                w[src + l] = wf;
-            }
+            if (sdf) sdf[src + l] = f;
+            if (w) w[src + l] = wf;
         }
     }
+    return ITM_OK;
+}
+
+itm_status itm_scene_enable_swapping(itm_scene *sc, int64_t device_blocks, int32_t swap_in, int32_t swap_out)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    if (sc->swap) return fail(ITM_ERR_STATE, "swapping is already on");
+    if (sc->frame != 0) return fail(ITM_ERR_STATE, "swapping must be enabled before the first frame");
+    if (sc->clr || sc->refiner) return fail(ITM_ERR_STATE, "swapping does not combine with colour or a refiner");
+    if (device_blocks < 1 || device_blocks > sc->n_entries || device_blocks > INT32_MAX)
+        return fail(ITM_ERR_ARG, "device_blocks %lld not in [1, %lld]", (long long)device_blocks,
+                    (long long)sc->n_entries);
+    if (swap_in < 1 || swap_out < 1 || swap_in > (1 << 20) || swap_out > (1 << 20))
+        return fail(ITM_ERR_ARG, "transfer sizes must be in [1, 2^20] blocks");
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    // the voxel block array becomes the device pool
+    (void)hipFree(sc->sdf);
+    (void)hipFree(sc->w);
+    sc->sdf = sc->w = nullptr;
+    sc->vba_cap = device_blocks;
+    const int64_t n_vox = device_blocks * kBlockVox;
+    const size_t es = sdf_elem(sc->fmt), ew = w_elem(sc->fmt);
+    const int32_t xcap = std::max(swap_in, swap_out);
+    if (itm_status st = dev_alloc(&sc->sdf, es * n_vox, "sdf")) return st;
+    if (itm_status st = dev_alloc(&sc->w, ew * n_vox, "weights")) return st;
+    if (dev_alloc((void **)&sc->blk, sizeof(int32_t) * sc->n_entries, "entry blocks") ||
+        dev_alloc((void **)&sc->onhost, sc->n_entries, "host flags") ||
+        dev_alloc((void **)&sc->pool_stack, sizeof(int32_t) * device_blocks, "block pool") ||
+        dev_alloc((void **)&sc->pool_top, sizeof(int32_t) * 2, "pool top") ||
+        dev_alloc((void **)&sc->pool_noblock, sizeof(unsigned long long), "pool misses") ||
+        dev_alloc((void **)&sc->swap_in_list, sizeof(SwapRec) * sc->n_entries, "swap-in candidates") ||
+        dev_alloc((void **)&sc->swap_out_list, sizeof(SwapRec) * sc->n_entries, "swap-out candidates") ||
+        dev_alloc((void **)&sc->swap_cnt, sizeof(int32_t) * 2, "swap counts") ||
+        dev_alloc(&sc->xfer_sdf, es * kBlockVox * (size_t)xcap, "transfer sdf") ||
+        dev_alloc(&sc->xfer_w, ew * kBlockVox * (size_t)xcap, "transfer weights") ||
+        dev_alloc((void **)&sc->xfer_entries, sizeof(int32_t) * xcap, "transfer entries"))
+        return ITM_ERR_OOM;
+    if (hipHostMalloc((void **)&sc->xfer_host, (es + ew) * kBlockVox * (size_t)xcap) != hipSuccess)
+        return fail(ITM_ERR_OOM, "pinned transfer buffer of %d blocks", xcap);
+    hipError_t e = launch_init(sc->buckets, sc->head, sc->n_buckets, sc->excess, sc->n_excess, sc->vis_stamp,
+                               sc->n_entries, sc->set, 2 * sc->set_size, sc->occ,
+                               sc->occ_words + kMacroWords + kBlockFilterWords, sc->cnt, sc->fmt, sc->sdf, sc->w,
+                               n_vox, sc->stream);
+    if (e == hipSuccess)
+        e = launch_swap_init(sc->pool_stack, (int32_t)device_blocks, sc->pool_top, sc->blk, sc->onhost,
+                             sc->n_entries, sc->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(sc->pool_noblock, 0, sizeof(unsigned long long), sc->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    if (e != hipSuccess) return fail(ITM_ERR_HIP, "swapping set-up failed: %s", hipGetErrorString(e));
+    sc->host_slot.assign(sc->n_entries, -1);
+    sc->host_data.clear();
+    sc->host_free.clear();
+    sc->swap_in_cap = swap_in;
+    sc->swap_out_cap = swap_out;
+    sc->swap = true;
+    return ITM_OK;
+}
+
+itm_status itm_swap_stats(itm_scene *sc, int64_t *out)
+{
+    if (!sc || !out) return fail(ITM_ERR_ARG, "NULL argument");
+    if (!sc->swap) return fail(ITM_ERR_STATE, "swapping is off");
+    std::vector<int32_t> dblk(sc->n_entries);
+    std::vector<uint8_t> onh(sc->n_entries);
+    int32_t top = 0;
+    unsigned long long nob = 0;
+    HIP_TRY(hipMemcpyAsync(dblk.data(), sc->blk, sizeof(int32_t) * sc->n_entries, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipMemcpyAsync(onh.data(), sc->onhost, sc->n_entries, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipMemcpyAsync(&top, sc->pool_top, sizeof top, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipMemcpyAsync(&nob, sc->pool_noblock, sizeof nob, hipMemcpyDeviceToHost, sc->stream));
+    HIP_TRY(hipStreamSynchronize(sc->stream));
+    int64_t n_dev = 0, host_only = 0, pending = 0;
+    for (int64_t e = 0; e < sc->n_entries; e++) {
+        n_dev += dblk[e] >= 0;
+        host_only += onh[e] && dblk[e] < 0;
+        pending += onh[e] && dblk[e] >= 0;
+    }
+    out[0] = n_dev;
+    out[1] = host_only;
+    out[2] = pending;
+    out[3] = sc->swapped_in_last;
+    out[4] = sc->swapped_out_last;
+    out[5] = sc->swapped_in_total;
+    out[6] = sc->swapped_out_total;
+    out[7] = (int64_t)nob;
+    (void)top;
+    return ITM_OK;
+}
+
+itm_status itm_import_blocks(itm_scene *sc, const int32_t *coords, const float *sdf, const float *w, int64_t n)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    if (sc->swap) return fail(ITM_ERR_STATE, "loading blocks does not combine with swapping");
+    if (n < 0 || n > (int64_t)INT32_MAX / 4) return fail(ITM_ERR_ARG, "n = %lld out of range", (long long)n);
+    if (n > 0 && (!coords || !sdf || !w)) return fail(ITM_ERR_ARG, "NULL coords, sdf or w");
+    // host checks: keys in range and distinct, values a valid voxel state
+    std::vector<int64_t> keys((size_t)n);
+    for (int64_t i = 0; i < n; i++) {
+        for (int c = 0; c < 3; c++)
+            if (coords[3 * i + c] < -32767 || coords[3 * i + c] > 32767)
+                return fail(ITM_ERR_ARG, "block %lld: coordinate %d out of the 16-bit range", (long long)i,
+                            coords[3 * i + c]);
+        keys[i] = ((int64_t)(coords[3 * i] + 32768) << 32) | ((int64_t)(coords[3 * i + 1] + 32768) << 16) |
+                  (int64_t)(coords[3 * i + 2] + 32768);
+    }
+    std::sort(keys.begin(), keys.end());
+    if (std::adjacent_find(keys.begin(), keys.end()) != keys.end())
+        return fail(ITM_ERR_ARG, "a block appears twice in the list");
+    for (int64_t i = 0; i < n * kBlockVox; i++) {
+        const float f = sdf[i], wv = w[i];
+        if (!(f >= -1.0f && f <= 1.0f)) return fail(ITM_ERR_ARG, "voxel %lld: F = %g not in [-1, 1]", (long long)i, f);
+        if (!(wv >= 0.0f && wv <= (float)sc->max_w) || wv != std::floor(wv))
+            return fail(ITM_ERR_ARG, "voxel %lld: W = %g is not an integer in [0, %d]", (long long)i, wv, sc->max_w);
+    }
+    // a frame of its own: find or insert every key, list it
+    FrameGeom g = {};
+    FuseArgs a = frame_args(sc, g, false);
+    int32_t *d_coords = nullptr, *d_entry = nullptr;
+    float *d_s = nullptr, *d_w = nullptr;
+    constexpr int64_t kChunk = 16384;   // blocks of voxels per copy (32 MiB per array)
+    const int64_t chunk = std::min<int64_t>(std::max<int64_t>(n, 1), kChunk);
+    itm_status st = dev_alloc((void **)&d_coords, sizeof(int32_t) * 3 * std::max<int64_t>(n, 1), "import keys");
+    if (!st) st = dev_alloc((void **)&d_entry, sizeof(int32_t) * std::max<int64_t>(n, 1), "import entries");
+    if (!st) st = dev_alloc((void **)&d_s, sizeof(float) * kBlockVox * chunk, "import sdf");
+    if (!st) st = dev_alloc((void **)&d_w, sizeof(float) * kBlockVox * chunk, "import weights");
+    hipError_t e = hipSuccess;
+    if (!st) {
+        if (n > 0) e = hipMemcpyAsync(d_coords, coords, sizeof(int32_t) * 3 * n, hipMemcpyHostToDevice, sc->stream);
+        if (e == hipSuccess) e = launch_import_keys(a, d_coords, (int32_t)n, d_entry, sc->stream);
+        for (int64_t off = 0; off < n && e == hipSuccess; off += chunk) {
+            const int64_t m = std::min(chunk, n - off);
+            e = hipMemcpyAsync(d_s, sdf + off * kBlockVox, sizeof(float) * kBlockVox * m, hipMemcpyHostToDevice,
+                               sc->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(d_w, w + off * kBlockVox, sizeof(float) * kBlockVox * m, hipMemcpyHostToDevice,
+                                   sc->stream);
+            if (e == hipSuccess)
+                e = launch_import_voxels(sc->fmt, d_entry + off, d_s, d_w, m, sc->sdf, sc->w, sc->clr, sc->stream);
+            // the staging buffers are reused by the next chunk
+            if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
+    }
+    (void)hipFree(d_coords);
+    (void)hipFree(d_entry);
+    (void)hipFree(d_s);
+    (void)hipFree(d_w);
+    if (st) return st;
+    if (e != hipSuccess) return fail(ITM_ERR_HIP, "import failed: %s", hipGetErrorString(e));
+    sc->fused_frame = -1;   // no bins at any pose: a search range re-bins the imported set
+    sc->frame++;
     return ITM_OK;
 }
 
@@ -1271,6 +1661,7 @@ itm_status itm_scene_set_refiner(itm_scene *sc, itm_refiner *r, float w_threshol
 {
     if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
     if (r && !(w_threshold > 0)) return fail(ITM_ERR_ARG, "weight threshold must be > 0");
+    if (r && sc->swap) return fail(ITM_ERR_STATE, "a refiner does not combine with swapping");
     if (r && !sc->refined) {
         if (dev_alloc((void **)&sc->refined, sizeof(__half) * kBlockVox * (size_t)sc->vba_cap, "refined F") ||
             dev_alloc((void **)&sc->stamp, sizeof(int32_t) * (size_t)sc->vba_cap, "refine stamps"))
@@ -1280,6 +1671,14 @@ itm_status itm_scene_set_refiner(itm_scene *sc, itm_refiner *r, float w_threshol
     sc->refiner = r;
     sc->refine_w_threshold = w_threshold;
     return ITM_OK;
+}
+
+itm_status itm_refine_visible(itm_scene *sc)
+{
+    if (!sc) return fail(ITM_ERR_ARG, "NULL scene");
+    if (!sc->refiner) return fail(ITM_ERR_STATE, "no refiner attached (itm_scene_set_refiner)");
+    if (sc->frame == 0) return fail(ITM_ERR_STATE, "no frame integrated or loaded yet");
+    return refine_visible(sc);
 }
 
 itm_status itm_export_blocks_refined(itm_scene *sc, int32_t *coords, float *sdf, uint8_t *refined,

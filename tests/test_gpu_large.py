@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from synth import make_stream
-from tests.gpu_util import compare_raycast, fuse_gpu
+from tests.gpu_util import compare_raycast, compare_volumes, fuse_gpu
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -26,12 +26,12 @@ def large_oracle():
             rays[f] = sc.raycast(st.width, st.height, st.intrinsics, st.T_wc[f])
         if f % 100 == 0:
             print(f"oracle frame {f}: {sc.stats()}", flush=True)
-    return st, sc.export(), sc.stats(), rays, max_vis
+    return st, sc.export(), sc.stats(), rays, max_vis, sc.export_candidates()
 
 
 @pytest.mark.parametrize("fmt", ["f32", "s16u8"])
 def test_large_full_stream(large_oracle, fmt):
-    st, (oc, oF, oW), ostats, orays, max_vis = large_oracle
+    st, (oc, oF, oW), ostats, orays, max_vis, cands = large_oracle
     print(f"case: large {fmt}", flush=True)
     g, grays, _ = fuse_gpu(st, fmt=fmt, ray_frames=RAY_FRAMES)
     gs = g.stats()
@@ -41,12 +41,14 @@ def test_large_full_stream(large_oracle, fmt):
     assert gs["n_dropped_total"] == ostats["n_dropped_total"]
     assert gs["n_excess_used"] == ostats["n_excess_used"]
     gc, gF, gW = g.export()
-    assert np.array_equal(gc, oc), "allocated block sets differ"
-    assert np.array_equal(gW.astype(np.int64), oW.astype(np.int64)), "weights differ"
+    if fmt == "f32":
+        tol = 1e-5
+    else:
+        def tol(W):
+            return (0.5 / 32767 + 4 * 2.0 ** -23) * (np.asarray(W, np.float64) + 1.0) + 1e-6
+    compare_volumes((gc, gF, gW), (oc, oF, oW), tol=tol, cands=cands)
     err = np.abs(gF.astype(np.float64) - oF)
-    tol = 1e-5 if fmt == "f32" else (0.5 / 32767 + 4 * 2.0 ** -23) * (oW + 1.0) + 1e-6
-    assert np.all(err <= tol), f"max |dF| {err.max():.3e}"
-    band = (oW > 0) & (np.abs(oF) < 1)
+    band = (oW > 0) & (np.abs(oF) < 1) & (gW.astype(np.int64) == oW)
     print(f"{fmt}: blocks {len(gc)}, max |dF| {err[band].max():.3e}, rms {np.sqrt(np.mean(err[band] ** 2)):.3e}")
     bar = 0.995 if fmt == "f32" else 0.99
     for f in RAY_FRAMES:

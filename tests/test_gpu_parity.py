@@ -1,8 +1,12 @@
 """GPU parity of the HIP path (through the C ABI) against the CPU oracle.
 
-Bars: the allocated block set and every voxel weight are bit-exact; |dF| <= 1e-5
-(|dSDF| <= 1e-5 mu) on every voxel; raycast camera depth within 0.5 mm on co-hit
-pixels (fraction bars, see gpu_util.compare_raycast)."""
+Bars: the allocated block set is bit-exact; every voxel's weight is bit-exact
+and |dF| <= 1e-5 (|dSDF| <= 1e-5 mu) against the oracle's binary64 state, or,
+where one of its updates took a decision within the binary32 error bound of a
+threshold, against one of the other states the oracle keeps for it
+(gpu_util.compare_volumes).  The end-to-end raycast of each side's own volume
+is held to fraction bars (gpu_util.compare_raycast); the raycast's per-pixel
+parity on identical volumes is in test_gpu_raycast.py."""
 import numpy as np
 import pytest
 
@@ -21,8 +25,8 @@ def test_tiny_f32_per_frame():
     for f, (a, b) in enumerate(zip(gstats, ostats)):
         assert a["n_visible_last"] == b["n_visible"], f
         assert a["n_allocated"] == b["n_allocated"], f
-        assert a["n_updated_last"] == b["n_updated_last"], f
-    mx, rms = compare_volumes(g.export(), o.export())
+        assert abs(a["n_updated_last"] - b["n_updated_last"]) <= b["n_ambiguous_last"], f
+    mx, rms, _ = compare_volumes(g.export(), o.export(), cands=o.export_candidates())
     print(f"max|dF| {mx:.2e} rms {rms:.2e}")
     for f in (0, 9):
         print(compare_raycast(grays[f], orays[f], st.T_wc[f]))
@@ -34,7 +38,7 @@ def test_vga_30_frames():
     g, grays, gstats = fuse_gpu(st, ray_frames=(29,))
     o, orays, ostats = fuse_oracle(st, ray_frames=(29,))
     assert g.stats()["n_excess_used"] == o.stats()["n_excess_used"]
-    mx, rms = compare_volumes(g.export(), o.export())
+    mx, rms, _ = compare_volumes(g.export(), o.export(), cands=o.export_candidates())
     print(f"max|dF| {mx:.2e} rms {rms:.2e}")
     print(compare_raycast(grays[29], orays[29], st.T_wc[29]))
 
@@ -45,7 +49,7 @@ def test_ragged_image_and_invalid_pixels():
     print("case: ragged 97x61 with invalid pixels", flush=True)
     g, grays, _ = fuse_gpu(st, ray_frames=(3,))
     o, orays, _ = fuse_oracle(st, ray_frames=(3,))
-    compare_volumes(g.export(), o.export())
+    compare_volumes(g.export(), o.export(), cands=o.export_candidates())
     print(compare_raycast(grays[3], orays[3], st.T_wc[3], min_cohit=0.99, min_close=0.99))
 
 
@@ -99,7 +103,7 @@ def test_side_stream():
         g, _, _ = fuse_gpu(st)
         out = g.export()
     o, _, _ = fuse_oracle(st)
-    compare_volumes(out, o.export())
+    compare_volumes(out, o.export(), cands=o.export_candidates())
 
 
 def test_invalid_arguments():
@@ -121,3 +125,18 @@ def test_invalid_arguments():
     T[0, 3] = np.nan
     with pytest.raises(itm.ItmError):
         sc.integrate(d, (100.0, 100.0, 5.0, 5.0, 10, 10), T)
+
+
+def test_out_of_memory_is_a_status():
+    """A table the device cannot hold (2^28 buckets: a 2.2 TB voxel block array)
+    fails with ITM_ERR_OOM, frees what it had allocated, and leaves the device
+    usable."""
+    itm, torch = gpu()
+    print("case: scene creation beyond HBM", flush=True)
+    with pytest.raises(itm.ItmError) as ei:
+        itm.Scene(0.01, 0.04, 100, 1 << 28, 1 << 20)
+    assert ei.value.status == itm.ITM_ERR_OOM, ei.value
+    st = make_stream("tiny", n_frames=2)
+    g, _, _ = fuse_gpu(st)
+    o, _, _ = fuse_oracle(st)
+    compare_volumes(g.export(), o.export(), cands=o.export_candidates())

@@ -2,8 +2,10 @@
 the paper's default stores a 16-bit SDF and an 8-bit weight) against the FP64
 oracle and against the plain binary32 form, on the full 300-frame VGA stream.
 
-Decisions do not depend on the storage form, so block sets and weights are
-bit-exact in every form.  Stored F carries quantisation error: each update
+Decisions do not depend on the storage form, so block sets are bit-exact and
+weights bit-exact against the oracle's states (its binary64 state, or another
+one it keeps where a decision lay within its binary32 error bound) in every
+form.  Stored F carries quantisation error: each update
 re-rounds, with error at most delta = half a storage step, and the running
 average forgets old error by W/(W+1), so the deviation from the exact average is
 bounded by delta * (W + 1) (below the weight cap (W+1)/2; at the cap max_w + 1).
@@ -14,22 +16,22 @@ import numpy as np
 import pytest
 
 from synth import make_stream
-from tests.gpu_util import (SDF_TOL, compare_raycast, fuse_gpu, fuse_oracle, camera_depth)
+from tests.gpu_util import (SDF_TOL, compare_raycast, compare_volumes, fuse_gpu, fuse_oracle, camera_depth)
 
 pytestmark = pytest.mark.gpu
 
 F32_EPS = 2.0 ** -23
 
 
-def bound(fmt, F_ref, W):
-    """Per-voxel bound delta * (W + 1); delta is half the storage step over the
-    whole range |F| <= 1 (a voxel's F can have been near 1 earlier in its
-    history): 1/(2*32767) for int16, 2^-12 for binary16 (step 2^-11 on [0.5, 1))."""
-    Wp1 = W.astype(np.float64) + 1.0
+def bound(fmt):
+    """Per-voxel bound delta * (W + 1) as a function of the weight W; delta is
+    half the storage step over the whole range |F| <= 1 (a voxel's F can have
+    been near 1 earlier in its history): 1/(2*32767) for int16, 2^-12 for
+    binary16 (step 2^-11 on [0.5, 1))."""
     if fmt == "f32":
-        return np.full(F_ref.shape, SDF_TOL)
+        return lambda W: SDF_TOL
     delta = (0.5 / 32767.0 if fmt == "s16u8" else 2.0 ** -12) + 4 * F32_EPS
-    return delta * Wp1 + 1e-6
+    return lambda W: delta * (np.asarray(W, np.float64) + 1.0) + 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -38,29 +40,27 @@ def vga_full():
     frames = (99, 299)
     print("case: vga 300 frames, oracle", flush=True)
     o, orays, ostats = fuse_oracle(st, ray_frames=frames)
-    return st, frames, o.export(), orays, o.stats()
+    return st, frames, o.export(), orays, o.stats(), o.export_candidates()
 
 
 @pytest.mark.parametrize("fmt", ["f32", "f16", "s16u8"])
 def test_vga_full_stream(vga_full, fmt):
-    st, frames, (oc, oF, oW), orays, ostats = vga_full
+    st, frames, (oc, oF, oW), orays, ostats, cands = vga_full
     print(f"case: vga 300 frames, {fmt}", flush=True)
     g, grays, _ = fuse_gpu(st, fmt=fmt, ray_frames=frames)
     gs = g.stats()
     assert gs["n_allocated"] == ostats["n_allocated"]
     assert gs["n_dropped_total"] == ostats["n_dropped_total"] == 0
     gc, gF, gW = g.export()
-    assert np.array_equal(gc, oc), "allocated block sets differ"
-    assert np.array_equal(gW.astype(np.int64), oW.astype(np.int64)), "weights differ"
+    _, _, info = compare_volumes((gc, gF, gW), (oc, oF, oW), tol=bound(fmt), cands=cands)
     err = np.abs(gF.astype(np.float64) - oF)
-    b = bound(fmt, oF, oW)
-    worst = np.argmax(err - b)
-    assert np.all(err <= b), f"{fmt}: |dF| {err.flat[worst]:.3e} > bound {b.flat[worst]:.3e}"
-    band = (oW > 0) & (np.abs(oF) < 1.0)
+    # errors inside the band, over voxels whose state is the oracle's binary64 one
+    band = (oW > 0) & (np.abs(oF) < 1.0) & (gW.astype(np.int64) == oW) & (err <= bound(fmt)(oW))
     mu = st.params["mu"]
     line = {"fmt": fmt, "blocks": int(len(gc)), "max_dSDF_m": float(err[band].max() * mu),
             "rms_dSDF_m": float(np.sqrt(np.mean(err[band] ** 2)) * mu),
-            "max_dF": float(err[band].max()), "rms_dF": float(np.sqrt(np.mean(err[band] ** 2)))}
+            "max_dF": float(err[band].max()), "rms_dF": float(np.sqrt(np.mean(err[band] ** 2))),
+            "candidate_voxels": info["n_candidate_voxels"], "gpu_took_other_state": info["n_alt"]}
     for f in frames:
         # binary32 storage holds the float path's bar; the quantised forms shift the
         # discrete march on a few more pixels (reported, bar 99%)

@@ -89,9 +89,13 @@ def test_adam_step_parity():
 def test_gather_parity():
     itm, torch = gpu()
     st = make_stream("tiny", n_frames=4)
-    g, _, _ = fuse_gpu(st)
     o, _, _ = fuse_oracle(st)
     oc, oF, oW = o.export()
+    # the oracle's volume loaded into the GPU scene (binary32 values): both
+    # sides hold the same voxels
+    oF = oF.astype(np.float32).astype(np.float64)
+    g = itm.Scene.from_params(st.params)
+    g.import_blocks(oc, oF.astype(np.float32), oW.astype(np.float32))
     pick = oc[:: max(1, len(oc) // 40)]
     got = g.gather(pick).cpu().numpy().reshape(-1, 2, 10, 10, 10)
     vol = {tuple(c): (f.reshape(8, 8, 8), w.reshape(8, 8, 8)) for c, f, w in zip(oc.tolist(), oF, oW)}
@@ -155,3 +159,99 @@ def test_gated_inference_in_integrate():
     assert np.abs(out - Fr[flags][:20]).max() <= 1e-3
     # unrefined blocks export the plain F
     assert np.array_equal(Fr[~flags], F[~flags])
+
+
+def haloed_inputs(coords, F, Wt, idx, max_w):
+    """network inputs [len(idx), 2, 10, 10, 10] of blocks idx of a volume (coords
+    [n, 3], F / W [n, 512]): F and W / max_w on voxels 8k-1 .. 8k+8, voxels of
+    absent blocks reading (1, 0)"""
+    pos = {tuple(c): i for i, c in enumerate(coords.tolist())}
+    F8 = F.reshape(-1, 8, 8, 8)          # [z][y][x]
+    W8 = Wt.reshape(-1, 8, 8, 8).astype(np.float64) / max_w
+    out = np.zeros((len(idx), 2, 10, 10, 10))
+    out[:, 0] = 1.0
+    for n, b in enumerate(idx):
+        kx, ky, kz = coords[b]
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    j = pos.get((kx + dx, ky + dy, kz + dz))
+                    if j is None:
+                        continue
+                    # the part of neighbour j inside the 10^3 window
+                    sl_dst, sl_src = [], []
+                    for d in (dz, dy, dx):
+                        if d == -1:
+                            sl_dst.append(slice(0, 1)); sl_src.append(slice(7, 8))
+                        elif d == 0:
+                            sl_dst.append(slice(1, 9)); sl_src.append(slice(0, 8))
+                        else:
+                            sl_dst.append(slice(9, 10)); sl_src.append(slice(0, 1))
+                    out[n, 0][tuple(sl_dst)] = F8[j][tuple(sl_src)]
+                    out[n, 1][tuple(sl_dst)] = W8[j][tuple(sl_src)]
+    return out
+
+
+def test_raycast_reads_refined_blocks():
+    """The raycast prefers a refined block's F: a volume the oracle fused from 2
+    frames (every block below the weight gate) is loaded into the GPU scene, the
+    refiner runs over it (itm_refine_visible), and the GPU raycast is held to the
+    oracle's raycast of the same volume with the gated blocks replaced by the
+    oracle's bf16-mode forward pass (stored as binary16, as the side buffer
+    is).  The network's values differ between the two by bf16 accumulation
+    order, so the bar is on the fraction of pixels within 0.5 mm; the refined
+    raycast must also differ from the plain one."""
+    import oracle
+    from tests.gpu_util import K_of, camera_depth
+    itm, torch = gpu()
+    st = make_stream("tiny", n_frames=2)
+    o, _, _ = fuse_oracle(st)
+    oc, oF, oW = o.export()
+    F32 = oF.astype(np.float32)
+    g = itm.Scene.from_params(st.params)
+    g.import_blocks(oc, F32, oW.astype(np.float32))
+    K = K_of(st)
+    T = st.T_wc[1]
+    p0, _ = g.raycast(K, T)
+    p = _params(7)
+    ref = itm.Refiner(p)
+    thr = 10.0
+    g.set_refiner(ref, thr)
+    g.refine_visible()
+    p1, n1 = g.raycast(K, T)
+    torch.cuda.synchronize()
+    gated = np.flatnonzero(oW.max(axis=1) < thr)
+    assert len(gated) == len(oc)          # two frames: every block is below the gate
+    inp = haloed_inputs(oc, F32.astype(np.float64), oW, gated, st.params["max_w"])
+    Fref = F32.astype(np.float64).copy()
+    for k in range(0, len(gated), 256):
+        Fref[gated[k:k + 256]] = R.forward_batch(inp[k:k + 256], p.astype(np.float64),
+                                                 bf16_mode=True).reshape(-1, 512)
+    Fref = Fref.astype(np.float16).astype(np.float64)
+    # the GPU's refined blocks (the side buffer) against the oracle's forward
+    gc, gF, flags = g.export_refined()
+    assert flags.all() and np.array_equal(gc, oc)
+    print(f"refined F: max |dF| {np.abs(gF - Fref).max():.2e}, moved by the net {np.abs(Fref - F32).max():.2e}")
+    assert np.abs(gF - Fref).max() < 5e-3   # bf16 sums in another order, then binary16
+    o2 = oracle.Scene.from_params(st.params)
+    o2.import_blocks(oc, Fref, oW)
+    opts, onrm, zc, fl, _ = o2.raycast(st.width, st.height, st.intrinsics, T)
+    P1 = p1.cpu().numpy()
+    ghit, ohit = P1[..., 3] > 0, opts[..., 3] > 0
+    z1 = camera_depth(P1, T)
+    both = ghit & ohit
+    close = (np.abs(z1 - zc)[both] <= 5e-4).mean()
+    print(f"refined raycast: hit/miss agree {(ghit == ohit).mean():.5f}, co-hit within 0.5 mm {close:.5f}")
+    assert (ghit == ohit).mean() >= 0.995 and close >= 0.995
+    # and the refiner changed what the raycast sees
+    P0 = p0.cpu().numpy()
+    z0 = camera_depth(P0, T)
+    moved = (np.abs(z1 - z0) > 1e-4)[both & (P0[..., 3] > 0)].mean()
+    print(f"pixels moved by more than 0.1 mm by the refiner: {moved:.3f}")
+    assert moved > 0.05
+    # detached: the plain raycast again, bit for bit
+    g.set_refiner(None)
+    p2, _ = g.raycast(K, T)
+    assert torch.equal(p2, p0)
+    g.close()
+    ref.close()

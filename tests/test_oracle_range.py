@@ -209,3 +209,21 @@ def test_range_bounds_are_obeyed(orc):
     late = full.copy()
     late[..., 0] = Z0 + 0.2
     assert not (sc.raycast(W, H, K, T[0], zrange=late)[0][..., 3] > 0).any()
+
+
+def test_raycast_reads_about_the_visible_blocks(orc):
+    """The benchmark prices a raycast's voxel reads by the frame's visible blocks
+    (512 F values and a bucket record each).  Counting what the oracle's ranged
+    raycast at the frame's pose actually reads, on the VGA stream: the distinct
+    blocks are within 5% of the visible ones, the buckets probed about 1.5x."""
+    from synth import make_stream
+    st = make_stream("vga", n_frames=20)
+    sc = orc.Scene.from_params(st.params)
+    for f in range(20):
+        sc.integrate(st.depth[f], st.intrinsics, st.T_wc[f])
+    args = (st.width, st.height, st.intrinsics, st.T_wc[19])
+    blocks, buckets = sc.raycast_touched(*args, zrange=sc.expected_depths(*args))
+    vis = sc.stats()["n_visible"]
+    print(f"visible {vis}, blocks read {blocks}, buckets probed {buckets}")
+    assert abs(blocks - vis) <= 0.05 * vis
+    assert vis <= buckets <= 2 * vis

@@ -129,3 +129,17 @@ def test_adam_matches_torch():
         opt.step()
         p, m, v = R.adam(p, g, m, v, k)
     assert np.abs(p - t.detach().numpy()).max() < 1e-12
+
+
+def test_forward_batch_is_forward_per_block():
+    rng = np.random.default_rng(5)
+    p = R.init_params(2)
+    W, b = R.unpack(p)
+    W[3, :, 0, :] = rng.standard_normal((27, 16)) * 0.05
+    b[:3] = rng.standard_normal((3, 16)) * 0.05
+    p = R.pack(W, b)
+    inp = np.stack([np.clip(rng.normal(0.2, 0.6, (3, 10, 10, 10)), -1, 1), rng.random((3, 10, 10, 10))], axis=1)
+    for mode in (False, True):
+        got = R.forward_batch(inp, p, bf16_mode=mode)
+        want = np.stack([R.forward(inp[i], p, bf16_mode=mode)[0] for i in range(3)])
+        assert np.abs(got - want).max() < 1e-12
