@@ -341,8 +341,12 @@ itm_status itm_track_noalloc(itm_scene *scene, const float *depth, const itm_int
 /* The raycast sees the blocks on the device only; itm_export_blocks returns    */
 /* every block wherever it is (merged when both copies exist).  Call before   */
 /* the first frame; not with colour, a refiner or itm_import_blocks            */
-/* (ITM_ERR_STATE).  ITM_ERR_ARG unless 1 <= device_blocks <= the entries and   */
-/* 1 <= swap_in, swap_out <= 2^20.  Synchronises the stream. */
+/* (ITM_ERR_STATE).  swap_in = swap_out = 0 keeps the pool without transfers: */
+/* the voxel block array is sized to device_blocks instead of one block per   */
+/* hash entry, and a block that finds the pool empty is not integrated        */
+/* (counted).  ITM_ERR_ARG unless 1 <= device_blocks <= the entries and either */
+/* both transfer sizes are 0 or 1 <= swap_in, swap_out <= 2^20.  Synchronises   */
+/* the stream. */
 itm_status itm_scene_enable_swapping(itm_scene *scene, int64_t device_blocks, int32_t swap_in,
                                      int32_t swap_out);
 /* out[8]: blocks holding a device block, blocks whose data is on the host     */

@@ -908,7 +908,7 @@ int64_t orc_import(orc_scene *sc, const int32_t *coords, const double *F, const 
 /* ------------------------------------------------------------------------- */
 int orc_enable_swapping(orc_scene *sc, int64_t dev_cap, int64_t in_cap, int64_t out_cap)
 {
-    if (sc->swap_on || dev_cap < 1 || in_cap < 1 || out_cap < 1 || sc->C) return -1;
+    if (sc->swap_on || dev_cap < 1 || in_cap < 0 || out_cap < 0 || sc->C) return -1;
     const int64_t nc = sc->cap_blocks ? sc->cap_blocks : 1;
     sc->dev = (uint8_t *)calloc((size_t)nc, 1);
     sc->host = (uint8_t *)calloc((size_t)nc, 1);

@@ -38,6 +38,7 @@ __device__ inline void frame_housekeeping(const FuseArgs &a)
             a.cnt->upd[a.parity ^ 1][threadIdx.x][0] = 0;
             a.cnt->vis[a.parity ^ 1][threadIdx.x][0] = 0;
         }
+        if (threadIdx.x == 0) a.cnt->unbinned[a.parity ^ 1][0] = 0;
         if (threadIdx.x < kListSegs) a.list_clear[32 * threadIdx.x] = 0;
         if (threadIdx.x == 0) *a.set_used_next = 0;
     }
@@ -360,27 +361,17 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
                 s_e[slot4[q]] = first ? e : -1;
                 if (first) device_block(a, e);
             } else if (e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) {
-                // the workgroup's set is full: list the block on its own, and bin
-                // its expected-depth rectangle on its own
+                // the workgroup's set is full: list the block on its own; its
+                // expected-depth rectangle is not binned, so the frame's bins are
+                // marked incomplete (every tile then computes its range exactly
+                // from the visible list)
                 device_block(a, e);
-                const int x = q == 0 ? cx[0] : q == 1 ? cx[1] : q == 2 ? cx[2] : cx[3];
-                const int y = q == 0 ? cy[0] : q == 1 ? cy[1] : q == 2 ? cy[2] : cy[3];
-                const int z = q == 0 ? cz[0] : q == 1 ? cz[1] : q == 2 ? cz[2] : cz[3];
                 VisRec r;
-                r.key = pack_key(x, y, z);
+                r.key = pack_key(cx[q & 3], cy[q & 3], cz[q & 3]);
                 r.e = e;
                 r.pad = 0;
                 a.list.rec[(int64_t)32 * a.list.cap + atomicAdd(&a.list.cnt[32 * 32], 1)] = r;
-                RangeRect rr;
-                if (a.rb.cnt && block_rect(g, x, y, z, rr)) {
-                    int tx0, ty0, ntx, n_tiles;
-                    rect_tiles(rr, tx0, ty0, ntx, n_tiles);
-                    for (int t = 0; t < n_tiles; t++) {
-                        const int tile = (ty0 + t / ntx) * a.rb.tw + tx0 + t % ntx;
-                        const int pos = atomicAdd(&a.rb.cnt[tile], 1);
-                        if (pos < a.rb.cap) a.rb.rect[(int64_t)tile * a.rb.cap + pos] = rr;
-                    }
-                }
+                if (a.rb.unbinned) *a.rb.unbinned = 1;
             }
         }
     }

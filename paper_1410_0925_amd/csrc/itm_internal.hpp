@@ -71,6 +71,9 @@ struct Counters {
     unsigned long long vis[3][kStripes][16];   // visible blocks
     // records appended to the visible list, [frame parity][segment], one line each
     int32_t lst[2][33][32];
+    // [frame parity][0]: the frame listed a block outside its workgroup's set and
+    // did not bin that block's rectangle (its bins then give no tile's range)
+    int32_t unbinned[2][32];
 };
 
 struct HashView {
@@ -260,6 +263,8 @@ struct RangeBins {
     RangeRect *rect;      // [n_tiles][cap]
     int32_t cap;
     int32_t tw, th;       // tiles per row, per column
+    int32_t *unbinned;    // non-null for bins the allocation fills: set when a block went
+                          // unbinned, and every tile then takes the exact path
 };
 
 // the per-frame kernels: allocation and visible list (and the expected-depth
@@ -669,6 +674,7 @@ __device__ __forceinline__ TileBin tile_bin(const RangeBins &rb, int tx, int ty)
     TileBin b;
     if ((int)threadIdx.x < rb.cap) b.first = rb.rect[(int64_t)tile * rb.cap + threadIdx.x];
     b.n = rb.cnt[tile];
+    if (rb.unbinned && *rb.unbinned) b.n = rb.cap + 1;   // incomplete bins: the exact path
     return b;
 }
 

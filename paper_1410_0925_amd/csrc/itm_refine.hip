@@ -4,10 +4,12 @@
 // block with a one-voxel halo, or the 8^3 block zero-padded) to the 8^3 block,
 // 16 input and 16 output channels (layer 1 uses 2 real input channels, layer 4
 // one real output channel; the others hold zeros).  As an implicit GEMM per
-// block: M = 512 voxels, N = 16 output channels, K = 27 taps x 16 channels, so one
-// tap is one K step of v_mfma_f32_16x16x16_bf16.  A workgroup of 4 waves takes a
-// block; wave w owns the voxel tiles 8w..8w+7.  Activations live in LDS as bf16
-// [voxel][channel]; weights are read from global memory (L1-resident) as bf16.
+// block: M = 512 voxels, N = 16 output channels, K = 27 taps x 16 channels, two
+// taps per K step of gfx950's v_mfma_f32_16x16x32_bf16 (layer 1, with its 2 real
+// input channels stored as 4, takes 8 taps per K step).  A workgroup of 4 waves
+// takes a block; wave w owns the voxel tiles 8w..8w+7.  Activations live in LDS
+// as bf16 [voxel][channel], so a lane's 8 K values are one 16-byte LDS read;
+// weights are read from global memory (L1-resident) as bf16.
 //
 // Back-propagation reuses the same operation: the data gradient is the
 // convolution of the output gradient with the tap-flipped, channel-transposed
@@ -22,6 +24,8 @@
 namespace itm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kC = 16, kTaps = 27, kLayers = 4;
@@ -41,65 +45,95 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
-// LDS working set of one block
-struct RefineLds {
-    uint16_t x0[1000 * 4];          // network input, 10^3 grid, channels F, W/max_w, 0, 0
-    uint16_t act[3][512 * kC];      // outputs of layers 1..3 (inputs of 2..4), 8^3 x 16
-    uint16_t grad[2][512 * kC];     // back-propagated gradient, ping-pong
-    float centre[512];              // F of the block itself (float32), for the residual
-};
-
-// A operand: 16 voxels x 4 channels of a layer input for one tap.
-// layer 0 reads the haloed 10^3 grid, later layers the zero-padded 8^3 block.
-__device__ __forceinline__ bf16x4 a_operand(const RefineLds &L, const uint16_t *in, int layer, int vox,
-                                            int tap, int kq)
+// 16 x 16 x 32: a lane holds 8 consecutive K values of its row (A) / column (B)
+__device__ __forceinline__ f32x4 mfma32(i32x4 a, i32x4 b, f32x4 c)
 {
-    const int x = vox & 7, y = (vox >> 3) & 7, z = vox >> 6;
-    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-    bf16x4 a = {0, 0, 0, 0};
-    if (layer == 0) {
-        if (kq == 0) {
-            const int u = (x + dx) + 10 * (y + dy) + 100 * (z + dz);
-            a = *reinterpret_cast<const bf16x4 *>(&L.x0[u * 4]);
-        }
-    } else {
-        const int ux = x + dx - 1, uy = y + dy - 1, uz = z + dz - 1;
-        if ((unsigned)ux < 8u && (unsigned)uy < 8u && (unsigned)uz < 8u)
-            a = *reinterpret_cast<const bf16x4 *>(&in[(ux + 8 * uy + 64 * uz) * kC + 4 * kq]);
-    }
-    return a;
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
 }
 
+// LDS working set of one block (16-byte aligned rows: a lane's 8 channels are one
+// read).  Training keeps all three hidden activations for the backward pass
+// (92 KB: one workgroup per CU); inference alternates two (42 KB: three).
+template <int NACT>
+struct alignas(16) RefineAct {
+    uint16_t x0[1000 * 4];          // network input, 10^3 grid, channels F, W/max_w, 0, 0
+    uint16_t act[NACT][512 * kC];   // layer l's output (8^3 x 16) in act[l % NACT]
+    float centre[512];              // F of the block itself (float32), for the residual
+};
+struct alignas(16) RefineLds : RefineAct<3> {
+    uint16_t grad[2][512 * kC];     // back-propagated gradient, ping-pong
+};
+using RefineLdsInf = RefineAct<2>;
+
 // one wave's 8 tiles of a 3^3 convolution: acc[t] (lane: voxel 4 kq + r of tile
-// 8 w + t, channel lane & 15) = sum over taps of A(tap) x W(tap)
-__device__ __forceinline__ void conv_tiles(const RefineLds &L, const uint16_t *in, int layer,
+// 8 w + t, channel lane & 15) = sum over taps of A(tap) x W(tap).
+// K order of one instruction (lane group kq = lane >> 4 holds K 8 kq .. 8 kq + 7):
+//   layer 0 (4 stored input channels): taps 8 g + 2 kq and 8 g + 2 kq + 1, their
+//            channels 0..3 each, g = 0..3 (taps past 26 read zeros);
+//   layers 1..3 and data gradients (16 channels): tap 2 p + (kq >> 1), channels
+//            8 (kq & 1) .. + 7, p = 0..13.
+__device__ __forceinline__ void conv_tiles(const uint16_t *x0, const uint16_t *in, int layer,
                                            const uint16_t *Wl, bool flip, int wave, int lane,
                                            f32x4 acc[8])
 {
     const int kq = lane >> 4, n = lane & 15;
+    const i32x4 zero = {0, 0, 0, 0};
 #pragma unroll
     for (int t = 0; t < 8; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < kTaps; tap++) {
+    if (layer == 0) {
+#pragma unroll 1
+        for (int g = 0; g < 4; g++) {
+            const int ta = 8 * g + 2 * kq, tb = ta + 1;
+            const bool va = ta < kTaps, vb = tb < kTaps;
+            const uint2 wa = va ? *reinterpret_cast<const uint2 *>(&Wl[(ta * kC + n) * kC]) : make_uint2(0, 0);
+            const uint2 wb = vb ? *reinterpret_cast<const uint2 *>(&Wl[(tb * kC + n) * kC]) : make_uint2(0, 0);
+            const i32x4 b = {(int)wa.x, (int)wa.y, (int)wb.x, (int)wb.y};
+            const int oa = (ta % 3) + 10 * ((ta / 3) % 3) + 100 * (ta / 9);
+            const int ob = (tb % 3) + 10 * ((tb / 3) % 3) + 100 * (tb / 9);
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+                const int vox = (wave * 8 + t) * 16 + n;
+                const int u = (vox & 7) + 10 * ((vox >> 3) & 7) + 100 * (vox >> 6);
+                const uint2 xa = va ? *reinterpret_cast<const uint2 *>(&x0[(u + oa) * 4]) : make_uint2(0, 0);
+                const uint2 xb = vb ? *reinterpret_cast<const uint2 *>(&x0[(u + ob) * 4]) : make_uint2(0, 0);
+                const i32x4 a = {(int)xa.x, (int)xa.y, (int)xb.x, (int)xb.y};
+                acc[t] = mfma32(a, b, acc[t]);
+            }
+        }
+        return;
+    }
+    const int h = kq & 1;
+#pragma unroll 1
+    for (int p = 0; p < (kTaps + 1) / 2; p++) {
+        const int tap = 2 * p + (kq >> 1);
+        const bool valid = tap < kTaps;
         const int wt = flip ? kTaps - 1 - tap : tap;
-        // B operand: 4 consecutive reduction channels of output column n
-        const bf16x4 b = *reinterpret_cast<const bf16x4 *>(&Wl[(wt * kC + n) * kC + 4 * kq]);
+        // B operand: 8 consecutive reduction channels of output column n
+        const i32x4 b = valid ? *reinterpret_cast<const i32x4 *>(&Wl[(wt * kC + n) * kC + 8 * h]) : zero;
+        const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
 #pragma unroll
         for (int t = 0; t < 8; t++) {
             const int vox = (wave * 8 + t) * 16 + n;
-            acc[t] = mfma16(a_operand(L, in, layer, vox, tap, kq), b, acc[t]);
+            const int ux = (vox & 7) + dx - 1, uy = ((vox >> 3) & 7) + dy - 1, uz = (vox >> 6) + dz - 1;
+            const bool inside = valid && (unsigned)ux < 8u && (unsigned)uy < 8u && (unsigned)uz < 8u;
+            const i32x4 a = inside ? *reinterpret_cast<const i32x4 *>(&in[(ux + 8 * uy + 64 * uz) * kC + 8 * h])
+                                   : zero;
+            acc[t] = mfma32(a, b, acc[t]);
         }
     }
 }
 
 // forward through the 4 layers; leaves activations in L.act and returns, for the
 // lanes with output channel 0, the residual delta of their 4 voxels per tile
-__device__ void refine_forward(RefineLds &L, const RefineParams &P, int wave, int lane, f32x4 delta[8])
+template <int NACT>
+__device__ void refine_forward(RefineAct<NACT> &L, const RefineParams &P, int wave, int lane, f32x4 delta[8])
 {
     const int kq = lane >> 4, n = lane & 15;
     f32x4 acc[8];
     for (int l = 0; l < kLayers; l++) {
-        const uint16_t *in = l == 0 ? nullptr : L.act[l - 1];
-        conv_tiles(L, in, l, P.Wf + (size_t)l * kTaps * kC * kC, false, wave, lane, acc);
+        const uint16_t *in = l == 0 ? nullptr : L.act[(l - 1) % NACT];
+        conv_tiles(L.x0, in, l, P.Wf + (size_t)l * kTaps * kC * kC, false, wave, lane, acc);
         const float b = P.bias[l * kC + n];
         if (l < kLayers - 1) {
 #pragma unroll
@@ -107,7 +141,7 @@ __device__ void refine_forward(RefineLds &L, const RefineParams &P, int wave, in
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
-                    L.act[l][vox * kC + n] = to_bf16(fmaxf(acc[t][r] + b, 0.0f));
+                    L.act[l % NACT][vox * kC + n] = to_bf16(fmaxf(acc[t][r] + b, 0.0f));
                 }
         } else {
 #pragma unroll
@@ -120,7 +154,8 @@ __device__ void refine_forward(RefineLds &L, const RefineParams &P, int wave, in
 }
 
 // fill L.x0 / L.centre from a float32 input block [2][10^3] in global memory
-__device__ void load_input(RefineLds &L, const float *in)
+template <int NACT>
+__device__ void load_input(RefineAct<NACT> &L, const float *in)
 {
     for (int u = threadIdx.x; u < 1000; u += blockDim.x) {
         const float F = in[u], W = in[1000 + u];
@@ -132,6 +167,30 @@ __device__ void load_input(RefineLds &L, const float *in)
         const int x = u % 10, y = (u / 10) % 10, z = u / 100;
         if (x >= 1 && x <= 8 && y >= 1 && y <= 8 && z >= 1 && z <= 8)
             L.centre[(x - 1) + 8 * (y - 1) + 64 * (z - 1)] = F;
+    }
+}
+
+// inference only: the refined F of each block
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_refine_infer(RefineArgs a)
+{
+    __shared__ RefineLdsInf L;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, n = lane & 15;
+    for (int64_t blk = blockIdx.x; blk < a.n; blk += gridDim.x) {
+        load_input(L, a.in + blk * 2000);
+        __syncthreads();
+        f32x4 delta[8];
+        refine_forward(L, a.P, wave, lane, delta);
+        if (n == 0) {
+#pragma unroll
+            for (int t = 0; t < 8; t++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    a.out[blk * 512 + vox] = fminf(fmaxf(L.centre[vox] + delta[t][r], -1.0f), 1.0f);
+                }
+        }
+        __syncthreads();
     }
 }
 
@@ -233,7 +292,7 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
             if (l == 0) break;
             // data gradient into the previous layer's output, masked by its ReLU
             f32x4 acc[8];
-            conv_tiles(L, G, 1, a.P.Wt + (size_t)l * kTaps * kC * kC, true, wave, lane, acc);
+            conv_tiles(L.x0, G, 1, a.P.Wt + (size_t)l * kTaps * kC * kC, true, wave, lane, acc);
             uint16_t *Gn = L.grad[cur ^ 1];
             const uint16_t *A = L.act[l - 1];
 #pragma unroll
@@ -251,24 +310,33 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
     }
 }
 
-// sum the per-block partial gradients in block order, divide by the batch's
-// count of supervised voxels
-__global__ void k_refine_reduce(const float *grad_part, const float *loss_part, int64_t n, float *grad,
-                                float *loss)
+// Sum the per-block partial gradients, divide by the batch's count of supervised
+// voxels.  A workgroup takes 64 parameters; its 4 waves each add a contiguous
+// quarter of the block rows (in row order), and the quarters are added in a fixed
+// order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(256) void k_refine_reduce(const float *grad_part, const float *loss_part, int64_t n,
+                                                       float *grad, float *loss)
 {
-    float cnt = 0.0f;
-    for (int64_t b = 0; b < n; b++) cnt += loss_part[2 * b + 1];
-    const float inv = 1.0f / fmaxf(cnt, 1.0f);
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < kNP) {
-        float s = 0.0f;
-        for (int64_t b = 0; b < n; b++) s += grad_part[b * kNP + p];
-        grad[p] = s * inv;
+    __shared__ float part[4][64];
+    __shared__ float s_inv;
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + lane;
+    const int64_t r0 = n * q / 4, r1 = n * (q + 1) / 4;
+    float acc = 0.0f;
+    if (p < kNP)
+        for (int64_t b = r0; b < r1; b++) acc += grad_part[b * kNP + p];
+    part[q][lane] = acc;
+    if (threadIdx.x == 0) {
+        float cnt = 0.0f;
+        for (int64_t b = 0; b < n; b++) cnt += loss_part[2 * b + 1];
+        s_inv = 1.0f / fmaxf(cnt, 1.0f);
     }
-    if (p == 0) {
+    __syncthreads();
+    if (q == 0 && p < kNP) grad[p] = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) * s_inv;
+    if (blockIdx.x == 0 && threadIdx.x == 64) {
         float sq = 0.0f;
         for (int64_t b = 0; b < n; b++) sq += loss_part[2 * b];
-        loss[0] = sq * inv;
+        loss[0] = sq * s_inv;
     }
 }
 
@@ -341,10 +409,10 @@ __global__ void k_refine_gather(HashView h, const void *sdf, const void *w, cons
 // volume into LDS and the refined F goes to a side buffer (half precision,
 // indexed like the voxel block array) stamped with the frame number.
 template <int FMT>
-__global__ __launch_bounds__(256) void k_refine_gated(RefineGateArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_refine_gated(RefineGateArgs a)
 {
     using V = Vox<FMT>;
-    __shared__ RefineLds L;
+    __shared__ RefineLdsInf L;
     __shared__ int s_go;
     const auto *S = (const typename V::S *)a.sdf;
     const auto *Wv = (const typename V::Wt *)a.w;
@@ -417,14 +485,14 @@ hipError_t launch_refine_gated(int fmt, const RefineGateArgs &a, int grid, hipSt
 hipError_t launch_refine(const RefineArgs &a, bool train, int grid, hipStream_t st)
 {
     if (train) k_refine<true><<<grid, 256, 0, st>>>(a);
-    else k_refine<false><<<grid, 256, 0, st>>>(a);
+    else k_refine_infer<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_refine_reduce(const float *grad_part, const float *loss_part, int64_t n, float *grad,
                                 float *loss, hipStream_t st)
 {
-    k_refine_reduce<<<(kNP + 255) / 256, 256, 0, st>>>(grad_part, loss_part, n, grad, loss);
+    k_refine_reduce<<<(kNP + 63) / 64, 256, 0, st>>>(grad_part, loss_part, n, grad, loss);
     return hipGetLastError();
 }
 

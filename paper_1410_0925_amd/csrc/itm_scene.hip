@@ -306,6 +306,7 @@ RangeBins bin_set(const itm_scene *sc, int set, int W, int H)
     rb.cap = sc->range_cap;
     rb.tw = (W + kTile - 1) / kTile;
     rb.th = (H + kTile - 1) / kTile;
+    rb.unbinned = set < 2 ? &sc->cnt->unbinned[set][0] : nullptr;   // set 2 is re-binned whole
     return rb;
 }
 
@@ -574,7 +575,7 @@ itm_status refine_visible(itm_scene *sc)
     ra.stamp = sc->stamp;
     ra.frame = sc->frame;
     ProfScope ps(sc, 3);
-    HIP_TRY(launch_refine_gated(sc->fmt, ra, sc->num_cu * 2, sc->stream));
+    HIP_TRY(launch_refine_gated(sc->fmt, ra, sc->num_cu * 3, sc->stream));
     return ITM_OK;
 }
 
@@ -729,7 +730,7 @@ itm_status integrate_frame(itm_scene *sc, const float *depth, const uchar4 *rgbx
         std::memcpy(sc->fused_T, T_wc, sizeof sc->fused_T);
     }
     sc->frame++;
-    if (sc->swap) return swap_frame(sc);
+    if (sc->swap && (sc->swap_in_cap > 0 || sc->swap_out_cap > 0)) return swap_frame(sc);
     if (sc->refiner) return refine_visible(sc);
     return ITM_OK;
 }
@@ -1024,8 +1025,9 @@ itm_status itm_scene_enable_swapping(itm_scene *sc, int64_t device_blocks, int32
     if (device_blocks < 1 || device_blocks > sc->n_entries || device_blocks > INT32_MAX)
         return fail(ITM_ERR_ARG, "device_blocks %lld not in [1, %lld]", (long long)device_blocks,
                     (long long)sc->n_entries);
-    if (swap_in < 1 || swap_out < 1 || swap_in > (1 << 20) || swap_out > (1 << 20))
-        return fail(ITM_ERR_ARG, "transfer sizes must be in [1, 2^20] blocks");
+    const bool pool_only = swap_in == 0 && swap_out == 0;   // a device pool without transfers
+    if (!pool_only && (swap_in < 1 || swap_out < 1 || swap_in > (1 << 20) || swap_out > (1 << 20)))
+        return fail(ITM_ERR_ARG, "transfer sizes must be in [1, 2^20] blocks (or both 0)");
     HIP_TRY(hipStreamSynchronize(sc->stream));
     // the voxel block array becomes the device pool
     (void)hipFree(sc->sdf);
@@ -1034,7 +1036,7 @@ itm_status itm_scene_enable_swapping(itm_scene *sc, int64_t device_blocks, int32
     sc->vba_cap = device_blocks;
     const int64_t n_vox = device_blocks * kBlockVox;
     const size_t es = sdf_elem(sc->fmt), ew = w_elem(sc->fmt);
-    const int32_t xcap = std::max(swap_in, swap_out);
+    const int32_t xcap = std::max(1, std::max(swap_in, swap_out));
     if (itm_status st = dev_alloc(&sc->sdf, es * n_vox, "sdf")) return st;
     if (itm_status st = dev_alloc(&sc->w, ew * n_vox, "weights")) return st;
     if (dev_alloc((void **)&sc->blk, sizeof(int32_t) * sc->n_entries, "entry blocks") ||
@@ -1595,7 +1597,7 @@ itm_status itm_refiner_forward(itm_refiner *r, const float *in, int64_t n, float
     a.in = in;
     a.n = n;
     a.out = out;
-    HIP_TRY(launch_refine(a, false, (int)std::min<int64_t>(n, (int64_t)r->num_cu * 2), r->stream));
+    HIP_TRY(launch_refine(a, false, (int)std::min<int64_t>(n, (int64_t)r->num_cu * 3), r->stream));
     return ITM_OK;
 }
 

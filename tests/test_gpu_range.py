@@ -126,3 +126,29 @@ def test_range_without_frames_and_toggling():
     assert _same(got, o.expected_depths(st.width, st.height, st.intrinsics, st.T_wc[1]))
     with pytest.raises(itm.ItmError):
         sc.set_search_range(True, 1 << 20)
+
+
+def test_blocks_listed_when_the_workgroup_set_is_full():
+    """A band far deeper than a block (voxel 3 mm, mu 0.5 m) makes a 16x16 tile's
+    pixels cross more distinct blocks (up to ~4200) than the allocation
+    kernel's per-workgroup set holds (2048): those blocks are listed, and their
+    rectangles binned, one by one.  Block set, visible count and the range image
+    at the frame's own pose (bins filled during allocation, room for every
+    rectangle) must still equal the oracle's."""
+    import oracle
+    itm, torch = gpu()
+    st = make_stream("tiny", n_frames=1)
+    params = dict(voxel_size=0.003, mu=0.5, max_w=100, n_buckets=2 ** 18, n_excess=2 ** 17)
+    print("case: tiny frame 0, voxel 3 mm, mu 0.5 m (workgroup sets overflow)", flush=True)
+    g = itm.Scene.from_params(params)
+    g.set_search_range(True, 8192)
+    g.integrate(torch.from_numpy(np.ascontiguousarray(st.depth[0])).cuda(), K_of(st), st.T_wc[0])
+    o = oracle.Scene.from_params(params)
+    n_vis = o.allocate(st.depth[0], st.intrinsics, st.T_wc[0])
+    assert g.stats()["n_visible_last"] == n_vis and g.stats()["n_allocated"] == o.stats()["n_allocated"]
+    gc = g.export(values=False)[0]
+    oc = o.export(with_values=False)[0]
+    assert np.array_equal(gc, oc)
+    got, want = _ranges(g, o, st, st.T_wc[0])
+    assert _same(got, want), f"{np.count_nonzero(got != want)} values differ"
+    g.close()

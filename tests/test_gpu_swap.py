@@ -88,3 +88,26 @@ def test_swapping_arguments():
         sc2.enable_colour()
     with pytest.raises(itm.ItmError):
         sc2.import_blocks(np.zeros((1, 3), np.int32), np.ones((1, 512), np.float32), np.zeros((1, 512), np.float32))
+
+
+def test_device_pool_without_transfers():
+    """Transfer sizes 0: the voxel block array is a pool of the given size
+    instead of one block per hash entry; with room for the map the volume is the
+    plain one."""
+    itm, torch = gpu()
+    st = make_stream("vga", n_frames=30)
+    print("case: vga 30 frames, a pool of 20000 blocks, no transfers", flush=True)
+    g = itm.Scene.from_params(st.params)
+    g.enable_swapping(20000, 0, 0)
+    depth = torch.from_numpy(np.ascontiguousarray(st.depth[:30])).cuda()
+    for f in range(30):
+        g.integrate(depth[f], K_of(st), st.T_wc[f])
+    torch.cuda.synchronize()
+    s = g.swap_stats()
+    assert s["no_block_total"] == 0 and s["swapped_out_total"] == 0 and s["n_host_only"] == 0
+    assert g.stats()["vba_capacity"] == 20000 < g.stats()["n_entries"]
+    o = oracle.Scene.from_params(st.params)
+    for f in range(30):
+        o.integrate(st.depth[f], st.intrinsics, st.T_wc[f])
+    compare_volumes(g.export(), o.export(), cands=o.export_candidates())
+    g.close()
