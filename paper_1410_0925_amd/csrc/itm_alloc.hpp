@@ -29,9 +29,11 @@ namespace itm {
 
 // Housekeeping of the kernel that opens a frame (the allocation, or a volume
 // import), every workgroup its share: the other parity's counters and list
-// counters, the next frame's claim count, the previous frame's claim slots and,
-// with the search range on, the other parity's bin counts are cleared.
-__device__ inline void frame_housekeeping(const FuseArgs &a)
+// counters, the next frame's claim count, the previous frame's claim slots (su
+// of them, read from *a.set_used_prev by the caller) and, with the search range
+// on, the other parity's bin counts are cleared.  Nothing the frame's kernel
+// itself uses is cleared, so the stores may go out at any point of it.
+__device__ inline void frame_housekeeping(const FuseArgs &a, int su)
 {
     if (blockIdx.x == 0) {
         if (threadIdx.x < kStripes) {
@@ -43,7 +45,6 @@ __device__ inline void frame_housekeeping(const FuseArgs &a)
         if (threadIdx.x == 0) *a.set_used_next = 0;
     }
     const int gt = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
-    const int su = *a.set_used_prev;
     for (int i = gt; i < su; i += gs) a.set_prev[a.set_list_prev[i]] = 0ull;
     if (a.rb_clear)
         for (int i = gt; i < a.n_clear; i += gs) a.rb_clear[i] = 0;
@@ -153,7 +154,8 @@ __device__ __forceinline__ int set_claim(unsigned long long *s_k, unsigned long 
 // pairs are first counted per tile in an LDS table, one global atomic per
 // distinct tile reserves the tile's slots, and the pairs then take consecutive
 // slots (a tile that finds the table full reserves pair by pair).  tab: LDS,
-// 4 * kBinTab ints (tile, pairs, cursor, base); n is uniform.
+// 4 * kBinTab ints (tile, pairs, cursor, base); n is uniform.  mid() runs on every
+// thread between the projections and the reservations, before a barrier.
 constexpr int kBinTab = 256;
 
 __device__ __forceinline__ int bin_tab_slot(int32_t *tab, int tile, bool insert)
@@ -168,8 +170,9 @@ __device__ __forceinline__ int bin_tab_slot(int32_t *tab, int tile, bool insert)
     return -1;
 }
 
+template <typename Mid>
 __device__ inline void bin_blocks(const FrameGeom &g, const RangeBins &rb, const unsigned long long *keys, int n,
-                                  int32_t *tab)
+                                  int32_t *tab, Mid mid)
 {
     const int corner = threadIdx.x & 7;
     for (int i = threadIdx.x; i < kBinTab; i += blockDim.x) {
@@ -197,6 +200,7 @@ __device__ inline void bin_blocks(const FrameGeom &g, const RangeBins &rb, const
             if (slot >= 0) atomicAdd(&tab[4 * slot + 1], 1);
         }
     }
+    mid();
     __syncthreads();
     // 2. one reservation per distinct tile
     for (int i = threadIdx.x; i < kBinTab; i += blockDim.x) {

@@ -279,7 +279,9 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
 
 // Allocation and visible list (itm_alloc.hpp), one thread per pixel:
 //   1. housekeeping, every workgroup its share: the previous frame's claim slots
-//      and, with the search range on, the next frame's bin counts are cleared;
+//      and, with the search range on, the next frame's bin counts are cleared
+//      (the stores go out after step 2, the one count they need is loaded with
+//      the depth);
 //   2. each thread walks its pixel's band segment and claims the blocks' keys in
 //      the workgroup's LDS set; the lane that claims a key first finds or inserts
 //      the block and records its entry there;
@@ -295,10 +297,19 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
     __shared__ int32_t s_e[kSet];
     __shared__ unsigned long long s_k[kSet];
     __shared__ int s_wave[4], s_n, s_base, s_ovf;
-    // 1. housekeeping
-    frame_housekeeping(a);
+    // the previous frame's claim count (for the housekeeping) and the pixel's
+    // depth are loaded first, together: one memory round before the allocation
+    const int su = *a.set_used_prev;
     int tx, ty;
-    if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;   // whole workgroup
+    if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) {   // whole workgroup
+        frame_housekeeping(a, su);
+        return;
+    }
+    const int u = tx * 16 + (threadIdx.x & 15);
+    const int v = ty * 16 + (threadIdx.x >> 4);
+    const bool in_image = u < g.W && v < g.H;
+    float depth = 0.0f;
+    if (in_image) depth = a.depth[(int64_t)v * g.W + u];
 #pragma unroll
     for (int j = 0; j < kSet / 256; j++) {
         s_e[threadIdx.x + 256 * j] = -1;
@@ -306,15 +317,10 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
     }
     __syncthreads();
     // 2. allocation
-    {
-        const int u = tx * 16 + (threadIdx.x & 15);
-        const int v = ty * 16 + (threadIdx.x >> 4);
-        if (u < g.W && v < g.H) {
-            const float depth = a.depth[(int64_t)v * g.W + u];
-            if (depth > 0.0f && !isinf(depth)) alloc_pixel(a, u, v, depth, s_e, s_k);
-        }
-    }
+    if (in_image && depth > 0.0f && !isinf(depth)) alloc_pixel(a, u, v, depth, s_e, s_k);
     __syncthreads();
+    // 1. housekeeping, its stores off the allocation's path
+    frame_housekeeping(a, su);
     // 3. the visible list: thread t takes set slots 8t..8t+7 (those its workgroup
     //    stamped first hold their entry)
     uint32_t win = 0;
@@ -340,7 +346,11 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
         went[j] = s_e[8 * threadIdx.x + j];
     }
     __syncthreads();
+    // thread 0 reserves the workgroup's list records; the reservation is consumed
+    // only after the binning's projections, which hide its round trip (barriers
+    // wait for LDS traffic, not for this atomic)
     const int stripe = blockIdx.x % 32;
+    int base = 0;
     if (threadIdx.x == 0) {
         int t = 0;
         for (int w = 0; w < 4; w++) {
@@ -348,38 +358,51 @@ __global__ __launch_bounds__(256) void k_alloc(FuseArgs a)
             s_wave[w] = t;
             t += x;
         }
-        int base = 0, ovf = 0;
-        if (t) {
-            base = atomicAdd(&a.list.cnt[32 * stripe], t);
-            // records past the stripe's capacity go to the overflow segment
-            const int spill = min(t, max(0, base + t - a.list.cap));
-            if (spill) ovf = atomicAdd(&a.list.cnt[32 * 32], spill);
-        }
         s_n = t;
-        s_base = base;
-        s_ovf = ovf;
+        // mbcnt of an empty mask is 0 on every lane, but not uniform to the
+        // compiler: the atomic stays a plain returning one, waited for where
+        // base is used, instead of a wave-aggregated one broadcast at once
+        if (t) base = atomicAdd(&a.list.cnt[32 * stripe + (int)__builtin_amdgcn_mbcnt_lo(0u, 0u)], t);
     }
     __syncthreads();
-    const int n_won = s_n, base = s_base, ovf = s_ovf;
-    int k = s_wave[wave] + incl - c;   // workgroup index of this thread's first record
+    const int n_won = s_n;
+    const int k0 = s_wave[wave] + incl - c;   // workgroup index of this thread's first record
+    {
+        int k = k0;
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            if (win & (1u << j)) s_k[k++] = wkey[j];   // the won keys, in list order, for the binning
+    }
+    auto publish = [&]() {
+        if (threadIdx.x != 0) return;
+        // records past the stripe's capacity go to the overflow segment
+        const int spill = min(n_won, max(0, base + n_won - a.list.cap));
+        s_ovf = spill ? atomicAdd(&a.list.cnt[32 * 32], spill) : 0;
+        s_base = base;
+    };
+    // 4. expected-depth rectangles
+    if (a.rb.cnt && n_won > 0) {   // uniform
+        __syncthreads();
+        bin_blocks(g, a.rb, s_k, n_won, s_e, publish);   // s_e is free again: its entries are in registers
+    } else {
+        publish();
+    }
+    __syncthreads();
+    const int lbase = s_base, ovf = s_ovf;
+    int k = k0;
 #pragma unroll
     for (int j = 0; j < 8; j++) {
         if (!(win & (1u << j))) continue;
         VisRec r;
-        r.key = wkey[j];
+        r.key = s_k[k];   // the binning only read the keys
         r.e = went[j];
         r.pad = 0;
-        const int pos = base + k;   // stripe position
+        const int pos = lbase + k;   // stripe position
         const int64_t slot = pos < a.list.cap ? (int64_t)stripe * a.list.cap + pos
-                                              : (int64_t)32 * a.list.cap + ovf + (pos - max(base, a.list.cap));
+                                              : (int64_t)32 * a.list.cap + ovf + (pos - max(lbase, a.list.cap));
         a.list.rec[slot] = r;
-        s_k[k] = wkey[j];   // the won keys, in list order, for the binning
         k++;
     }
-    // 4. expected-depth rectangles
-    if (!a.rb.cnt || n_won == 0) return;   // uniform
-    __syncthreads();
-    bin_blocks(g, a.rb, s_k, n_won, s_e);   // s_e is free again: its entries are in registers
 }
 
 // Integration: one wave per visible block.  Wave gw serves list stripe
@@ -444,7 +467,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
 // entry); entry[i] = the block's entry (= its voxel block), -1 when dropped.
 __global__ __launch_bounds__(256) void k_import_keys(FuseArgs a, const int32_t *coords, int32_t n, int32_t *entry)
 {
-    frame_housekeeping(a);
+    frame_housekeeping(a, *a.set_used_prev);
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int bx = coords[3 * i], by = coords[3 * i + 1], bz = coords[3 * i + 2];
