@@ -47,16 +47,26 @@ _LIB_NATIVE = os.path.join(_HERE, f"liboracle_native_{_host_tag()}.so")
 CFLAGS_NATIVE = ["-O3", "-march=native"] + [f for f in CFLAGS if f != "-O2"]
 
 
+def _stale(path: str) -> bool:
+    """whether a build is missing or older than the source"""
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)
+
+
+def _compile(path: str, flags) -> None:
+    tmp = path + f".tmp{os.getpid()}"   # concurrent test workers each write their own
+    subprocess.check_call(["gcc", *flags, "-o", tmp, _SRC, "-lm"])
+    os.replace(tmp, path)
+
+
 def use_native_build() -> str:
-    """Load the -O3 -march=native build (compiled here if missing) instead of the
-    default one; must be called before any other oracle call."""
+    """Load the -O3 -march=native build (compiled here if missing or older than
+    the source) instead of the default one; must be called before any other
+    oracle call."""
     global _LIB
     if _lib is not None and _LIB != _LIB_NATIVE:
         raise RuntimeError("the oracle library is already loaded")
-    if not os.path.exists(_LIB_NATIVE):
-        tmp = _LIB_NATIVE + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", *CFLAGS_NATIVE, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_NATIVE)
+    if _stale(_LIB_NATIVE):
+        _compile(_LIB_NATIVE, CFLAGS_NATIVE)
     _LIB = _LIB_NATIVE
     return _LIB
 
@@ -65,10 +75,8 @@ def build(force: bool = True) -> str:
     for f in os.listdir(_HERE):   # host builds: rebuilt from the current source when next used
         if f.startswith("liboracle_native_") and f.endswith(".so"):
             os.remove(os.path.join(_HERE, f))
-    if force or not os.path.exists(_LIB_DEFAULT):
-        tmp = _LIB_DEFAULT + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_DEFAULT)
+    if force or _stale(_LIB_DEFAULT):
+        _compile(_LIB_DEFAULT, CFLAGS)
     return _LIB_DEFAULT
 
 
@@ -84,8 +92,8 @@ def _ptr(a):
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
+        if _stale(_LIB):   # missing, or the source changed since it was built
+            _compile(_LIB, CFLAGS_NATIVE if _LIB == _LIB_NATIVE else CFLAGS)
         L = C.CDLL(_LIB)
         sig = {
             "orc_hash_index": (_u32, [_i32, _i32, _i32, _u32]),

@@ -509,9 +509,11 @@ int64_t orc_allocate(orc_scene *sc, const float *depth, int W, int H, const doub
 /* decisions take; a candidate follows each outcome of each later frame.  The   */
 /* error bounds (u = 2^-24, unit roundoff of binary32) assume an evaluation     */
 /* whose error is relative to the camera point itself (a camera-space point    */
-/* exact to binary32 within the voxel's block, plus at most 3 x 7 voxel steps): */
+/* exact to binary32 within the voxel's block, plus at most 3 x 7 voxel steps), */
+/* and a quotient p_x / p_z formed as p_x times a reciprocal of p_z accurate to */
+/* one ulp (relative error 3 u: 2 u for the reciprocal, u for the product):     */
 /*   e_p   = 1.5 u max|p_a| + 24 u s            per component of p              */
-/*   e_x   = fx ((e_p (1 + |X|)) / p_z + u |X|) + u (fx |X| + 2 |x| + |cx|),     */
+/*   e_x   = fx ((e_p (1 + |X|)) / p_z + 3 u |X|) + u (fx |X| + 2 |x| + |cx|),   */
 /*           X = p_x / p_z (likewise y)                                         */
 /*   e_eta = e_p + 2 u (|d| + |p_z| + |eta|)                                   */
 /* and tau = 2 e (a factor two of headroom).  A voxel whose candidate set would  */
@@ -634,9 +636,9 @@ static int orc_outcomes(const orc_frame *fr, const int64_t *v, orc_outcome *out,
     const int z_tie = p[2] <= 2.0 * ep;
     const double X = p[0] / p[2], Y = p[1] / p[2];
     const double x = c->fx * X + c->cx, y = c->fy * Y + c->cy;
-    const double tx = 2.0 * (c->fx * ((ep * (1.0 + fabs(X))) / p[2] + ORC_U * fabs(X)) +
+    const double tx = 2.0 * (c->fx * ((ep * (1.0 + fabs(X))) / p[2] + 3.0 * ORC_U * fabs(X)) +
                              ORC_U * (c->fx * fabs(X) + 2.0 * fabs(x) + fabs(c->cx)));
-    const double ty = 2.0 * (c->fy * ((ep * (1.0 + fabs(Y))) / p[2] + ORC_U * fabs(Y)) +
+    const double ty = 2.0 * (c->fy * ((ep * (1.0 + fabs(Y))) / p[2] + 3.0 * ORC_U * fabs(Y)) +
                              ORC_U * (c->fy * fabs(Y) + 2.0 * fabs(y) + fabs(c->cy)));
     const double xmax = (double)(c->W - 2), ymax = (double)(c->H - 2);
     const int inside = x >= 1.0 && x <= xmax && y >= 1.0 && y <= ymax;

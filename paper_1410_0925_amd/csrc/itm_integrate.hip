@@ -180,8 +180,9 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
                 }
                 pix[j] = 0;
                 if (p[2] <= 0.0f) continue;
-                const float x = g.fx * p[0] / p[2] + g.cx;
-                const float y = g.fy * p[1] / p[2] + g.cy;
+                const float rz = __builtin_amdgcn_rcpf(p[2]);   // 1 ulp; one reciprocal for x and y
+                const float x = g.fx * p[0] * rz + g.cx;
+                const float y = g.fy * p[1] * rz + g.cy;
                 if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
                 pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
                 seen[grp] |= 1u << j;
@@ -234,8 +235,9 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
                 }
                 eta[j] = 0.0f;
                 if (p[2] <= 0.0f) continue;
-                const float x = g.fx * p[0] / p[2] + g.cx;
-                const float y = g.fy * p[1] / p[2] + g.cy;
+                const float rz = __builtin_amdgcn_rcpf(p[2]);
+                const float x = g.fx * p[0] * rz + g.cx;
+                const float y = g.fy * p[1] * rz + g.cy;
                 if (x < 1.0f || x > (float)(g.W - 2) || y < 1.0f || y > (float)(g.H - 2)) continue;
                 pix[j] = (int)(x + 0.5f) + (int)(y + 0.5f) * g.W;
                 smp[j] = a.rgbx[pix[j]];   // with the depth: no dependent read later
@@ -256,8 +258,9 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
                 const float f = fminf(1.0f, eta[j] * inv_mu);
                 const float F = v.F(j), W = v.Wv(j);
                 const float Wn = W + 1.0f;
-                // running average F <- (W F + f) / (W + 1), in incremental form
-                const float Fn = F + (f - F) / Wn;
+                // running average F <- (W F + f) / (W + 1), in incremental form (the
+                // reciprocal of the integer W + 1 to 1 ulp)
+                const float Fn = F + (f - F) * __builtin_amdgcn_rcpf(Wn);
                 v.set(j, Fn, fminf(Wn, g.max_w_f));
             }
             v.store(a.sdf, a.w, vbase + li0);
