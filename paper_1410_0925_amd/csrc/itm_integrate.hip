@@ -166,18 +166,17 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
         for (int grp = 0; grp < 2; grp++) {
             const int li0 = 4 * lane + 256 * grp;
             const float fy_ = (float)((li0 >> 3) & 7), fz_ = (float)(li0 >> 6);
+            // the group's y and z steps, shared by its 4 voxels
+            float yz[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) yz[c] = fy_ * g.g[1][c] + fz_ * g.g[2][c];
             int pix[4];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const float fx_ = (float)((li0 & 7) + j);
                 float p[3];
 #pragma unroll
-                for (int c = 0; c < 3; c++) {
-                    float t = fx_ * g.g[0][c];
-                    t = t + fy_ * g.g[1][c];
-                    t = t + fz_ * g.g[2][c];
-                    p[c] = hi[c] + (lo[c] + t);
-                }
+                for (int c = 0; c < 3; c++) p[c] = hi[c] + (lo[c] + (fx_ * g.g[0][c] + yz[c]));
                 pix[j] = 0;
                 if (p[2] <= 0.0f) continue;
                 const float rz = __builtin_amdgcn_rcpf(p[2]);   // 1 ulp; one reciprocal for x and y
@@ -204,6 +203,7 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
         uchar4 smp[4];
         uint32_t upd = 0, cupd = 0;
         if constexpr (!CLR) {
+            const float yz2 = fy_ * g.g[1][2] + fz_ * g.g[2][2];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 eta[j] = 0.0f;
@@ -211,9 +211,7 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
                 const float d = dep[grp][j];
                 if (!(d > 0.0f) || isinf(d)) continue;
                 // the voxel's camera-z step, as in its projection (same operations)
-                float dl2 = (float)((li0 & 7) + j) * g.g[0][2];
-                dl2 = dl2 + fy_ * g.g[1][2];
-                dl2 = dl2 + fz_ * g.g[2][2];
+                const float dl2 = (float)((li0 & 7) + j) * g.g[0][2] + yz2;
                 const float e32 = (d - hi[2]) - (lo[2] + dl2);
                 if (e32 < -mu) continue;
                 eta[j] = e32;
@@ -221,15 +219,16 @@ __device__ uint32_t integrate_block(const FuseArgs &a, unsigned long long key, i
             }
         } else {
             // the colour form keeps one voxel at a time (its registers are full)
+            float yz[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) yz[c] = fy_ * g.g[1][c] + fz_ * g.g[2][c];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
                 const float fx_ = (float)((li0 & 7) + j);
                 float p[3], dl2 = 0.0f;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    float t = fx_ * g.g[0][c];
-                    t = t + fy_ * g.g[1][c];
-                    t = t + fz_ * g.g[2][c];
+                    const float t = fx_ * g.g[0][c] + yz[c];
                     p[c] = hi[c] + (lo[c] + t);
                     if (c == 2) dl2 = t;
                 }
@@ -498,7 +497,7 @@ hipError_t launch_import_keys(const FuseArgs &a, const int32_t *coords, int32_t 
 
 hipError_t launch_alloc(const FuseArgs &a, hipStream_t st)
 {
-    k_alloc<<<xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16)), 256, 0, st>>>(a);
+    launch_k(k_alloc, xcd_grid(((a.fg.W + 15) / 16) * ((a.fg.H + 15) / 16)), 256, st, a);
     return hipGetLastError();
 }
 
@@ -506,12 +505,12 @@ hipError_t launch_integrate(int fmt, const FuseArgs &a, int grid, hipStream_t st
 {
     const bool clr = a.clr && a.rgbx;
     switch (fmt * 2 + (clr ? 1 : 0)) {
-    case 2 * ITM_VOX_F32: k_integrate<ITM_VOX_F32, false><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_F32 + 1: k_integrate<ITM_VOX_F32, true><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_F16: k_integrate<ITM_VOX_F16, false><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_F16 + 1: k_integrate<ITM_VOX_F16, true><<<grid, 256, 0, st>>>(a); break;
-    case 2 * ITM_VOX_S16U8 + 1: k_integrate<ITM_VOX_S16U8, true><<<grid, 256, 0, st>>>(a); break;
-    default: k_integrate<ITM_VOX_S16U8, false><<<grid, 256, 0, st>>>(a); break;
+    case 2 * ITM_VOX_F32: launch_k(k_integrate<ITM_VOX_F32, false>, grid, 256, st, a); break;
+    case 2 * ITM_VOX_F32 + 1: launch_k(k_integrate<ITM_VOX_F32, true>, grid, 256, st, a); break;
+    case 2 * ITM_VOX_F16: launch_k(k_integrate<ITM_VOX_F16, false>, grid, 256, st, a); break;
+    case 2 * ITM_VOX_F16 + 1: launch_k(k_integrate<ITM_VOX_F16, true>, grid, 256, st, a); break;
+    case 2 * ITM_VOX_S16U8 + 1: launch_k(k_integrate<ITM_VOX_S16U8, true>, grid, 256, st, a); break;
+    default: launch_k(k_integrate<ITM_VOX_S16U8, false>, grid, 256, st, a); break;
     }
     return hipGetLastError();
 }

@@ -28,6 +28,7 @@
 // 2 n_buckets + x for excess entry x.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <climits>
@@ -36,6 +37,28 @@
 #include "itm.h"
 
 namespace itm {
+
+// Events a profiled launch attaches to its dispatch (hipExtLaunchKernelGGL: they
+// take the kernel's own start and end times, not those of markers queued around
+// it).  The host sets them for the next launch on its thread; launch_k consumes
+// them, and a plain launch is made when none are set.
+struct DispatchEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+DispatchEvents &dispatch_events();
+
+template <typename... KArgs, typename... Args>
+inline void launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t st, Args... args)
+{
+    DispatchEvents &ev = dispatch_events();
+    if (ev.start) {
+        const DispatchEvents e = ev;
+        ev = DispatchEvents{};
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e.start, e.stop, 0, args...);
+    } else {
+        kernel<<<grid, block, 0, st>>>(args...);
+    }
+}
 
 constexpr int kBlockVox = 512;
 constexpr unsigned long long kKeyValid = 1ull << 63;

@@ -404,11 +404,11 @@ template <int FMT>
 void launch_fmt(const RaycastArgs &a, bool clr, bool ref, int grid, hipStream_t st)
 {
     if (ref) {
-        if (clr) k_raycast<FMT, true, true><<<grid, 256, 0, st>>>(a);
-        else k_raycast<FMT, false, true><<<grid, 256, 0, st>>>(a);
+        if (clr) launch_k(k_raycast<FMT, true, true>, grid, 256, st, a);
+        else launch_k(k_raycast<FMT, false, true>, grid, 256, st, a);
     } else {
-        if (clr) k_raycast<FMT, true, false><<<grid, 256, 0, st>>>(a);
-        else k_raycast<FMT, false, false><<<grid, 256, 0, st>>>(a);
+        if (clr) launch_k(k_raycast<FMT, true, false>, grid, 256, st, a);
+        else launch_k(k_raycast<FMT, false, false>, grid, 256, st, a);
     }
 }
 

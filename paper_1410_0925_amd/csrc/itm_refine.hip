@@ -475,9 +475,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 hipError_t launch_refine_gated(int fmt, const RefineGateArgs &a, int grid, hipStream_t st)
 {
     switch (fmt) {
-    case ITM_VOX_F32: k_refine_gated<ITM_VOX_F32><<<grid, 256, 0, st>>>(a); break;
-    case ITM_VOX_F16: k_refine_gated<ITM_VOX_F16><<<grid, 256, 0, st>>>(a); break;
-    default: k_refine_gated<ITM_VOX_S16U8><<<grid, 256, 0, st>>>(a); break;
+    case ITM_VOX_F32: launch_k(k_refine_gated<ITM_VOX_F32>, grid, 256, st, a); break;
+    case ITM_VOX_F16: launch_k(k_refine_gated<ITM_VOX_F16>, grid, 256, st, a); break;
+    default: launch_k(k_refine_gated<ITM_VOX_S16U8>, grid, 256, st, a); break;
     }
     return hipGetLastError();
 }

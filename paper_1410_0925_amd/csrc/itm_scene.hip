@@ -333,6 +333,7 @@ itm_status prof_flush(itm_scene *sc)
     if (sc->ev_used == 0) return ITM_OK;
     HIP_TRY(hipStreamSynchronize(sc->stream));
     for (int i = 0; i < sc->ev_used; i++) {
+        if (sc->ev_kernel[i] < 0) continue;   // its launch never took the events
         float ms = 0;
         HIP_TRY(hipEventElapsedTime(&ms, sc->ev[2 * i], sc->ev[2 * i + 1]));
         sc->prof_ms[sc->ev_kernel[i]] += ms;
@@ -342,7 +343,19 @@ itm_status prof_flush(itm_scene *sc)
     return ITM_OK;
 }
 
-// record events around one launch when profiling is on
+}  // namespace
+
+itm::DispatchEvents &itm::dispatch_events()
+{
+    static thread_local DispatchEvents ev;
+    return ev;
+}
+
+namespace {
+
+// when profiling is on, the next launch (the one this scope wraps) carries a pair
+// of events on its dispatch; a scope whose launch did not take them (an error
+// before it) leaves its slot out
 struct ProfScope {
     itm_scene *sc;
     int slot = -1;
@@ -352,11 +365,14 @@ struct ProfScope {
         if (sc->ev_used == kProfSlots && prof_flush(sc) != ITM_OK) return;
         slot = sc->ev_used++;
         sc->ev_kernel[slot] = kernel;
-        (void)hipEventRecord(sc->ev[2 * slot], sc->stream);
+        dispatch_events() = DispatchEvents{sc->ev[2 * slot], sc->ev[2 * slot + 1]};
     }
     ~ProfScope()
     {
-        if (slot >= 0) (void)hipEventRecord(sc->ev[2 * slot + 1], sc->stream);
+        if (slot >= 0 && dispatch_events().start) {
+            dispatch_events() = DispatchEvents{};
+            sc->ev_kernel[slot] = -1;
+        }
     }
 };
 

@@ -196,13 +196,13 @@ hipError_t launch_track_init(const PoseInit &a, hipStream_t st)
 
 hipError_t launch_icp_sums(const IcpArgs &a, int grid, hipStream_t st)
 {
-    k_icp_sums<<<grid, 256, 0, st>>>(a);
+    launch_k(k_icp_sums, grid, 256, st, a);
     return hipGetLastError();
 }
 
 hipError_t launch_icp_solve(const SolveArgs &a, hipStream_t st)
 {
-    k_icp_solve<<<1, 1024, 0, st>>>(a);
+    launch_k(k_icp_solve, 1, 1024, st, a);
     return hipGetLastError();
 }
 
