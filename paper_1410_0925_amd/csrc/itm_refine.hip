@@ -322,22 +322,41 @@ __global__ __launch_bounds__(256) void k_refine_reduce(const float *grad_part, c
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
     const int64_t r0 = n * q / 4, r1 = n * (q + 1) / 4;
+    // the quarter's rows added in row order, eight loads in flight ahead of the
+    // additions
     float acc = 0.0f;
-    if (p < kNP)
-        for (int64_t b = r0; b < r1; b++) acc += grad_part[b * kNP + p];
+    if (p < kNP) {
+        int64_t b = r0;
+        for (; b + 8 <= r1; b += 8) {
+            float v[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) v[k] = grad_part[(b + k) * kNP + p];
+#pragma unroll
+            for (int k = 0; k < 8; k++) acc += v[k];
+        }
+        for (; b < r1; b++) acc += grad_part[b * kNP + p];
+    }
     part[q][lane] = acc;
-    if (threadIdx.x == 0) {
-        float cnt = 0.0f;
-        for (int64_t b = 0; b < n; b++) cnt += loss_part[2 * b + 1];
-        s_inv = 1.0f / fmaxf(cnt, 1.0f);
+    if (q == 0) {
+        // the counted voxels (integers, exact in any order) and, for the loss,
+        // the squared errors: the first wave, a fixed butterfly, lane 0's sums
+        float cnt = 0.0f, sq = 0.0f;
+        for (int64_t b = lane; b < n; b += 64) {
+            cnt += loss_part[2 * b + 1];
+            if (blockIdx.x == 0) sq += loss_part[2 * b];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            cnt += __shfl_xor(cnt, o, 64);
+            sq += __shfl_xor(sq, o, 64);
+        }
+        if (lane == 0) {
+            s_inv = 1.0f / fmaxf(cnt, 1.0f);
+            if (blockIdx.x == 0) loss[0] = sq * s_inv;
+        }
     }
     __syncthreads();
     if (q == 0 && p < kNP) grad[p] = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) * s_inv;
-    if (blockIdx.x == 0 && threadIdx.x == 64) {
-        float sq = 0.0f;
-        for (int64_t b = 0; b < n; b++) sq += loss_part[2 * b];
-        loss[0] = sq * s_inv;
-    }
 }
 
 // Adam on float32 master weights, then the two bf16 copies
