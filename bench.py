@@ -30,20 +30,20 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 
 
 # Hardware byte counters of the depth-only kernels on this workload, KiB per
-# dispatch, averaged over the bench's timed frames 10..299 (search range on), from
-#   rocprofv3 --pmc FETCH_SIZE (resp. WRITE_SIZE) -- python3 bench.py
-#   --no-cpu-baseline --no-learned --no-colour --no-events --calib-copy-mb 256
+# dispatch, averaged over the timed frames 10..299 (search range on) of
+#   rocprofv3 --pmc FETCH_SIZE (resp. WRITE_SIZE) --output-format csv -- python3 bench.py
+#   --no-cpu-baseline --no-learned --no-colour --no-track --calib-copy-mb 256
 # (summaries under profiles/).  FETCH_SIZE counts 64 B per read request while
 # these kernels' read requests are 128 B (TCC_EA0_RDREQ_128B): the reference
-# elementwise kernel that reads 256 MiB reports 131,088 KiB, hence the factor 2;
+# elementwise kernel that reads 256 MiB reports 131,087 KiB, hence the factor 2;
 # WRITE_SIZE reports the 256 MiB it writes exactly.  `src` is a SHA-256 prefix of
-# the kernel's source files when the counters were taken; a changed kernel
-# reports traffic null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.9, 262144.0 / 262144.0
+# the kernel's source files when the counters were taken; a changed kernel, or
+# another frame range, reports traffic null.
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.4, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga"): {"fetch": 1046.2, "write": 1034.6, "src": "bbfbd137ed09399d"},
-    ("integrate", "f32", "vga"): {"fetch": 10049.4, "write": 14769.0, "src": "bbfbd137ed09399d"},
-    ("raycast", "f32", "vga"): {"fetch": 7397.7, "write": 9600.0, "src": "02ec27a622b92ddc"},
+    ("alloc", "f32", "vga", "10..299"): {"fetch": 1065.3, "write": 1036.0, "src": "94de00370f248ea9"},
+    ("integrate", "f32", "vga", "10..299"): {"fetch": 10047.3, "write": 14769.6, "src": "94de00370f248ea9"},
+    ("raycast", "f32", "vga", "10..299"): {"fetch": 7403.0, "write": 9600.0, "src": "89b2239786ee18a1"},
 }
 
 
