@@ -79,8 +79,6 @@ __device__ inline int32_t find_or_insert(const FuseArgs &a, int bx, int by, int 
             if (i == 0) atomicOr(&h.occ[b >> 5], 1u << (b & 31));  // slot 0 fills first
             const uint32_t m = macro_index(bx, by, bz);
             atomicOr(&h.macro[m >> 5], 1u << (m & 31));
-            const uint32_t f = bfilt_index(bx, by, bz);
-            atomicOr(&h.bfilt[f >> 5], 1u << (f & 31));
             return 2 * (int32_t)b + i;
         }
         if (old == key) return 2 * (int32_t)b + i;
@@ -113,8 +111,6 @@ __device__ inline int32_t find_or_insert(const FuseArgs &a, int bx, int by, int 
     {
         const uint32_t m = macro_index(bx, by, bz);
         atomicOr(&h.macro[m >> 5], 1u << (m & 31));
-        const uint32_t f = bfilt_index(bx, by, bz);
-        atomicOr(&h.bfilt[f >> 5], 1u << (f & 31));
     }
     // link at the end of the chain; every failed compare-and-swap means another
     // claimant linked first, so the walk moves on and terminates

@@ -106,8 +106,6 @@ struct HashView {
     uint32_t *occ;      // one bit per bucket: set once the bucket holds a block
     uint32_t *macro;    // kMacroBits bits, one per hashed macro cell (4^3 blocks): set
                         // once any block of a cell hashing there is allocated
-    uint32_t *bfilt;    // kBlockFilterBits bits, one per hashed block: set once a block
-                        // hashing there is allocated
     uint32_t mask;
     int32_t n_buckets;
     int32_t n_excess;
@@ -449,23 +447,15 @@ __device__ __forceinline__ bool xcd_tile(int n_tx, int n_ty, int &tx, int &ty)
 }
 __host__ __forceinline__ int xcd_grid(int n_tiles) { return (n_tiles + kXcds - 1) / kXcds * kXcds; }
 
-// Two small hashed occupancy filters, staged in LDS by the raycast: no false
-// negatives, so a clear bit proves a block (or a whole macro cell) absent.
+// A small hashed occupancy filter of macro cells, staged in LDS by the raycast:
+// no false negatives, so a clear bit proves a whole macro cell absent.
 constexpr int kMacroShift = 2;              // macro cell = 4 x 4 x 4 blocks
 constexpr int kMacroBits = 1 << 16;         // 8 KiB
 constexpr int kMacroWords = kMacroBits / 32;
-constexpr int kBlockFilterBits = 1 << 17;   // 16 KiB
-constexpr int kBlockFilterWords = kBlockFilterBits / 32;
 
 __device__ __forceinline__ uint32_t macro_index(int bx, int by, int bz)
 {
     return hash_index(bx >> kMacroShift, by >> kMacroShift, bz >> kMacroShift, kMacroBits - 1);
-}
-__device__ __forceinline__ uint32_t bfilt_index(int bx, int by, int bz)
-{
-    // the low bits of the bucket hash: a test followed by a probe of the same
-    // block computes the products once
-    return hash_index(bx, by, bz, kBlockFilterBits - 1);
 }
 
 // retrieval without the bucket bitmap, for blocks that are probably allocated
@@ -473,16 +463,6 @@ __device__ __forceinline__ int32_t find_block_direct(const HashView &h, int x, i
 {
     if (!in_key_range(x, y, z)) return -1;
     return probe_bucket(h, hash_index(x, y, z, h.mask), pack_key(x, y, z));
-}
-
-// retrieval behind the block filter (filt: the filter's words, e.g. staged in
-// LDS): -1 without a probe when the filter proves the block absent
-__device__ __forceinline__ int32_t find_block_filtered(const HashView &h, const uint32_t *filt, int x, int y, int z)
-{
-    const uint32_t hr = hash_raw(x, y, z);
-    const uint32_t fi = hr & (kBlockFilterBits - 1);
-    if (!((filt[fi >> 5] >> (fi & 31)) & 1u) || !in_key_range(x, y, z)) return -1;
-    return probe_bucket(h, hr & h.mask, pack_key(x, y, z));
 }
 
 // key of hash entry e (entry ids as in the layout above); the block is e itself

@@ -16,9 +16,10 @@
 // t += F_t mu once behind the surface); the normal is the normalised central
 // difference of F_t at +-1 voxel along the world axes.
 // A one-entry register cache of the last block looked up saves most hash probes:
-// consecutive samples of a ray mostly fall in the same block.  Coarse samples in
-// space with no allocated block are skipped a macro cell (4^3 blocks) at a time
-// through a hashed occupancy bitmap; the samples taken keep the 8 s spacing.
+// consecutive samples of a ray mostly fall in the same block, and a probe is one
+// load of the bucket's two keys.  Coarse samples in space with no allocated block
+// are skipped a macro cell (4^3 blocks) at a time through a hashed occupancy
+// bitmap staged in LDS; the samples taken keep the 8 s spacing.
 #include "itm_internal.hpp"
 
 namespace itm {
@@ -46,19 +47,18 @@ template <int FMT, bool REF>
 struct BlockReader {
     const HashView &h;
     VoxSrc<FMT, REF> src;
-    const uint32_t *filt;   // block filter in LDS
     int cx, cy, cz;
     int32_t cptr;
     bool cref;              // the cached block reads its refined F
 
-    __device__ BlockReader(const HashView &hv, const VoxSrc<FMT, REF> &s, const uint32_t *f)
-        : h(hv), src(s), filt(f), cx(INT_MIN), cy(0), cz(0), cptr(-1), cref(false) {}
+    __device__ BlockReader(const HashView &hv, const VoxSrc<FMT, REF> &s)
+        : h(hv), src(s), cx(INT_MIN), cy(0), cz(0), cptr(-1), cref(false) {}
 
     __device__ int32_t block(int bx, int by, int bz)
     {
         if (bx != cx || by != cy || bz != cz) {
             cx = bx; cy = by; cz = bz;
-            cptr = block_of(h, find_block_filtered(h, filt, bx, by, bz));
+            cptr = block_of(h, find_block_direct(h, bx, by, bz));
             if (REF) cref = src.refined(cptr);
         }
         return cptr;
@@ -91,11 +91,11 @@ struct Cube {
                (lz >> 3) >= bz0 && (hz >> 3) <= bz1;
     }
 
-    // every block is probed unless the LDS block filter proves it absent (the
-    // march's cached block is not reused: keeping it live costs registers)
+    // every block is probed (the march's cached block is not reused: keeping it
+    // live costs registers)
     template <bool REF>
-    __device__ void fetch(const HashView &h, const uint32_t *filt, const VoxSrc<FMT, REF> &src, int lx, int ly,
-                          int lz, int hx, int hy, int hz)
+    __device__ void fetch(const HashView &h, const VoxSrc<FMT, REF> &src, int lx, int ly, int lz, int hx, int hy,
+                          int hz)
     {
         bx0 = lx >> 3; by0 = ly >> 3; bz0 = lz >> 3;
         bx1 = hx >> 3; by1 = hy >> 3; bz1 = hz >> 3;
@@ -105,7 +105,7 @@ struct Cube {
             const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
             const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
             const int kx = dx ? bx1 : bx0, ky = dy ? by1 : by0, kz = dz ? bz1 : bz0;
-            p[c] = need ? block_of(h, find_block_filtered(h, filt, kx, ky, kz)) : -1;
+            p[c] = need ? block_of(h, find_block_direct(h, kx, ky, kz)) : -1;
         }
         rmask = 0u;
         if (REF) {
@@ -215,15 +215,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const FrameGeom &g = a.fg;
     int tx, ty;
     if (!xcd_tile((g.W + 15) / 16, (g.H + 15) / 16, tx, ty)) return;  // whole workgroup
-    // the tile's expected-depth bin, loaded while the filters are staged
+    // the tile's expected-depth bin, loaded while the macro filter is staged
     TileBin bin;
     if (a.rb.cnt) bin = tile_bin(a.rb, tx, ty);
-    // the macro-cell and block filters, staged in LDS: empty-space tests cost an
-    // LDS read (they are contiguous in global memory)
-    __shared__ uint32_t s_filt[kMacroWords + kBlockFilterWords];
+    // the macro-cell filter, staged in LDS: empty-space tests cost an LDS read
+    __shared__ uint32_t s_filt[kMacroWords];
     {   // all of a thread's reads issued before its LDS writes: one round trip
-        constexpr int kPer = (kMacroWords + kBlockFilterWords) / 4 / 256;
-        static_assert(kPer * 4 * 256 == kMacroWords + kBlockFilterWords, "filters fill whole 256-thread rounds");
+        constexpr int kPer = kMacroWords / 4 / 256;
+        static_assert(kPer * 4 * 256 == kMacroWords, "the filter fills whole 256-thread rounds");
         const uint4 *src = reinterpret_cast<const uint4 *>(a.h.macro);
         uint4 *dst = reinterpret_cast<uint4 *>(s_filt);
         uint4 w[kPer];
@@ -280,13 +279,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
     const float idz = dz != 0.0f ? 1.0f / dz : 0.0f;
     const float inv_bs = 1.0f / bs;
 
-    const uint32_t *s_bfilt = s_filt + kMacroWords;
     VoxSrc<FMT, REF> src;
     src.sdf = (const typename Vox<FMT>::S *)a.sdf;
     src.ref = a.refined;
     src.stamp = a.rstamp;
     src.frame = a.rframe;
-    BlockReader<FMT, REF> rd(a.h, src, s_bfilt);
+    BlockReader<FMT, REF> rd(a.h, src);
     float t = t_near;
     int state = RC_COARSE, fine_miss = 0;
     for (int it = 0; it < cap && t < t_far; it++) {
@@ -349,7 +347,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         float fx = floorf(qx), fy = floorf(qy), fz = floorf(qz);
         int ix = (int)fx, iy = (int)fy, iz = (int)fz;
         Cube<FMT> cb;
-        cb.fetch(a.h, s_bfilt, src, ix - 3, iy - 3, iz - 3, ix + 4, iy + 4, iz + 4);
+        cb.fetch(a.h, src, ix - 3, iy - 3, iz - 3, ix + 4, iy + 4, iz + 4);
         float Fc[8];
         cube_cell(cb, sdf, ix, iy, iz, Fc);
         t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
@@ -363,7 +361,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
         int jx = (int)fx, jy = (int)fy, jz = (int)fz;
         if (!cb.holds(jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3))
-            cb.fetch(a.h, s_bfilt, src, jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3);
+            cb.fetch(a.h, src, jx - 2, jy - 2, jz - 2, jx + 3, jy + 3, jz + 3);
         if (jx != ix || jy != iy || jz != iz) cube_cell(cb, sdf, jx, jy, jz, Fc);
         t = fmaf(trilinear8(Fc, qx - fx, qy - fy, qz - fz), mu, t);
         // The normal: central differences of F_t over the stencil of the final
@@ -372,7 +370,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
         fx = floorf(qx); fy = floorf(qy); fz = floorf(qz);
         ix = (int)fx; iy = (int)fy; iz = (int)fz;
         if (!cb.holds(ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2))
-            cb.fetch(a.h, s_bfilt, src, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
+            cb.fetch(a.h, src, ix - 1, iy - 1, iz - 1, ix + 2, iy + 2, iz + 2);
         float Ex[2][4], Ey[2][4], Ez[2][4];   // [minus/plus][(a, b) of the other two axes]
         stencil(cb, sdf, ix, iy, iz, ix == jx && iy == jy && iz == jz, Fc, Ex, Ey, Ez);
         float gx = 0.0f, gy = 0.0f, gz = 0.0f;

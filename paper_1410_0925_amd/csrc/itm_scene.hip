@@ -320,7 +320,6 @@ HashView hash_view(const itm_scene *sc)
     h.excess = sc->excess;
     h.occ = sc->occ;
     h.macro = sc->occ + sc->occ_words;
-    h.bfilt = h.macro + kMacroWords;
     h.mask = sc->mask;
     h.n_buckets = (int32_t)sc->n_buckets;
     h.n_excess = (int32_t)sc->n_excess;
@@ -482,14 +481,14 @@ itm_scene *itm_scene_create_ex(float voxel_size, float mu, int32_t max_w, int64_
         dev_alloc((void **)&sc->set_list, sizeof(int32_t) * 3 * sc->set_size, "claim lists") ||
         dev_alloc((void **)&sc->cnt, sizeof(Counters), "counters") ||
         dev_alloc((void **)&sc->occ,
-                  sizeof(uint32_t) * ((n_buckets + 31) / 32 + kMacroWords + kBlockFilterWords),
+                  sizeof(uint32_t) * ((n_buckets + 31) / 32 + kMacroWords),
                   "occupancy bitmaps")) {
         release(sc);
         return nullptr;
     }
     sc->occ_words = (n_buckets + 31) / 32;
     hipError_t e = launch_init(sc->buckets, sc->head, n_buckets, sc->excess, n_excess, sc->vis_stamp, sc->n_entries,
-                               sc->set, 2 * sc->set_size, sc->occ, sc->occ_words + kMacroWords + kBlockFilterWords,
+                               sc->set, 2 * sc->set_size, sc->occ, sc->occ_words + kMacroWords,
                                sc->cnt, fmt, sc->sdf, sc->w, n_vox, sc->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(sc->stream);
     if (e != hipSuccess) {
@@ -1071,7 +1070,7 @@ itm_status itm_scene_enable_swapping(itm_scene *sc, int64_t device_blocks, int32
         return fail(ITM_ERR_OOM, "pinned transfer buffer of %d blocks", xcap);
     hipError_t e = launch_init(sc->buckets, sc->head, sc->n_buckets, sc->excess, sc->n_excess, sc->vis_stamp,
                                sc->n_entries, sc->set, 2 * sc->set_size, sc->occ,
-                               sc->occ_words + kMacroWords + kBlockFilterWords, sc->cnt, sc->fmt, sc->sdf, sc->w,
+                               sc->occ_words + kMacroWords, sc->cnt, sc->fmt, sc->sdf, sc->w,
                                n_vox, sc->stream);
     if (e == hipSuccess)
         e = launch_swap_init(sc->pool_stack, (int32_t)device_blocks, sc->pool_top, sc->blk, sc->onhost,
