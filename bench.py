@@ -232,7 +232,7 @@ def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True
     return out
 
 
-def kernel_replay(itm, torch, st, depth, K, fmt, ranged, first, n, rgb=None):
+def kernel_replay(itm, torch, st, depth, K, fmt, ranged, first, n, rgb=None, pool=0):
     """Frames 0..first+n-1 on a fresh scene; frames first.. carry an event pair
     around every launch (on the scene's stream).  The launches are enqueued
     back to back and synchronised once at the end.  With rgb (colour images on
@@ -242,6 +242,8 @@ def kernel_replay(itm, torch, st, depth, K, fmt, ranged, first, n, rgb=None):
     nrm = torch.empty_like(pts)
     crgb = torch.empty((K[5], K[4], 4), dtype=torch.uint8, device="cuda")
     sc = itm.Scene.from_params(st.params, fmt=fmt)
+    if pool:
+        sc.enable_swapping(pool, 0, 0)   # a device pool of `pool` blocks, no transfers
     sc.set_search_range(ranged)
     if rgb is not None:
         sc.enable_colour()
@@ -332,6 +334,9 @@ def main():
     ap.add_argument("--colour-steps", type=int, default=None,
                     help="frames timed in the colour leg (default: the same frames as the main loop)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--pool-blocks", type=int, default=0,
+                    help="size the voxel block array to this many blocks (a device pool, "
+                         "no transfers) instead of one block per hash entry")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the timed region, copy a buffer of this size once "
                          "(reference kernel for hardware byte counters)")
@@ -367,6 +372,8 @@ def main():
     nrm = torch.empty((H, W, 4), dtype=torch.float32, device="cuda")
 
     sc = itm.Scene.from_params(st.params, fmt=args.fmt)
+    if args.pool_blocks:
+        sc.enable_swapping(args.pool_blocks, 0, 0)
     ranged = args.search_range == "on"
     sc.set_search_range(ranged)
     for f in range(args.warmup):
@@ -404,7 +411,7 @@ def main():
     if not args.no_events:
         log("per-kernel events: replay of the timed frames")
         prof, rep = kernel_replay(itm, torch, st, depth, K, args.fmt, ranged, args.warmup,
-                                  max(20, args.steps))
+                                  max(20, args.steps), pool=args.pool_blocks)
     kernels, best = {}, None
     for name in ("alloc", "integrate", "raycast"):
         ms, launches = prof.get(name, (0.0, 0))
@@ -454,7 +461,8 @@ def main():
                                f"{frames}, voxel "
                                f"{p['voxel_size']} m, mu {p['mu']} m, 2^{int(np.log2(p['n_buckets']))} "
                                f"buckets + 2^{int(np.log2(p['n_excess']))} excess, raycast {W}x{H}",
-                   "storage": args.fmt, "search_range": "expected depths" if ranged else "z_near..z_far"},
+                   "storage": args.fmt, "search_range": "expected depths" if ranged else "z_near..z_far",
+                   "voxel_blocks": args.pool_blocks if args.pool_blocks else "one per hash entry"},
         "rays_per_s": rays / wall,
         "updated_voxels_per_s": upd_total / wall,
         "visible_blocks_per_frame": vis_total / args.steps,
@@ -462,6 +470,12 @@ def main():
         "kernels": kernels,
         "roofline": roofline,
     }
+    free_b, total_b = torch.cuda.mem_get_info()
+    out["device_memory_in_use_GiB"] = round((total_b - free_b) / 2**30, 2)   # scene, stream, torch buffers
+    if args.pool_blocks:
+        sw = sc.swap_stats()
+        out["voxel_pool"] = {"blocks": args.pool_blocks, "held_after_timed_frames": int(sw["n_device"]),
+                             "visible_blocks_left_without_one": int(sw["no_block_total"])}
     if not args.no_track:
         log("depth tracker: last frame against the raycast at the frame before")
         out["track"] = track_leg(itm, torch, sc, st, depth, K, args.warmup + args.steps - 1, 20,
