@@ -39,11 +39,11 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 # WRITE_SIZE reports the 256 MiB it writes exactly.  `src` is a SHA-256 prefix of
 # the kernel's source files when the counters were taken; a changed kernel, or
 # another frame range, reports traffic null.
-FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.4, 262144.0 / 262144.0
+FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.7, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga", "10..299"): {"fetch": 1065.3, "write": 1036.0, "src": "94de00370f248ea9"},
-    ("integrate", "f32", "vga", "10..299"): {"fetch": 10047.3, "write": 14769.6, "src": "94de00370f248ea9"},
-    ("raycast", "f32", "vga", "10..299"): {"fetch": 7403.0, "write": 9600.0, "src": "89b2239786ee18a1"},
+    ("alloc", "f32", "vga", "10..299"): {"fetch": 1064.4, "write": 1034.8, "src": "bcc4e73df3cd6340"},
+    ("integrate", "f32", "vga", "10..299"): {"fetch": 10050.7, "write": 14769.2, "src": "bcc4e73df3cd6340"},
+    ("raycast", "f32", "vga", "10..299"): {"fetch": 7452.8, "write": 9600.0, "src": "423391ee41704a05"},
 }
 
 
