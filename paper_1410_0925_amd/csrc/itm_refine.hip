@@ -6,8 +6,10 @@
 // one real output channel; the others hold zeros).  As an implicit GEMM per
 // block: M = 512 voxels, N = 16 output channels, K = 27 taps x 16 channels, two
 // taps per K step of gfx950's v_mfma_f32_16x16x32_bf16 (layer 1, with its 2 real
-// input channels stored as 4, takes 8 taps per K step).  A workgroup of 4 waves
-// takes a block; wave w owns the voxel tiles 8w..8w+7.  Activations live in LDS
+// input channels stored as 4, takes 8 taps per K step).  A workgroup of 16 waves
+// takes a block; wave w owns the voxel tiles 2w, 2w + 1 of its 32 (16-voxel
+// tiles), so each SIMD has 4 waves to overlap LDS reads and MFMA chains (the
+// LDS footprint allows few workgroups per CU).  Activations live in LDS
 // as bf16 [voxel][channel], so a lane's 8 K values are one 16-byte LDS read;
 // weights are read from global memory (L1-resident) as bf16.
 //
@@ -66,21 +68,22 @@ struct alignas(16) RefineLds : RefineAct<3> {
 };
 using RefineLdsInf = RefineAct<2>;
 
-// one wave's 8 tiles of a 3^3 convolution: acc[t] (lane: voxel 4 kq + r of tile
-// 8 w + t, channel lane & 15) = sum over taps of A(tap) x W(tap).
+// one wave's TPW tiles of a 3^3 convolution: acc[t] (lane: voxel 4 kq + r of tile
+// TPW w + t, channel lane & 15) = sum over taps of A(tap) x W(tap).
 // K order of one instruction (lane group kq = lane >> 4 holds K 8 kq .. 8 kq + 7):
 //   layer 0 (4 stored input channels): taps 8 g + 2 kq and 8 g + 2 kq + 1, their
 //            channels 0..3 each, g = 0..3 (taps past 26 read zeros);
 //   layers 1..3 and data gradients (16 channels): tap 2 p + (kq >> 1), channels
 //            8 (kq & 1) .. + 7, p = 0..13.
+template <int TPW>
 __device__ __forceinline__ void conv_tiles(const uint16_t *x0, const uint16_t *in, int layer,
                                            const uint16_t *Wl, bool flip, int wave, int lane,
-                                           f32x4 acc[8])
+                                           f32x4 acc[TPW])
 {
     const int kq = lane >> 4, n = lane & 15;
     const i32x4 zero = {0, 0, 0, 0};
 #pragma unroll
-    for (int t = 0; t < 8; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < TPW; t++) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (layer == 0) {
 #pragma unroll 1
         for (int g = 0; g < 4; g++) {
@@ -92,8 +95,8 @@ __device__ __forceinline__ void conv_tiles(const uint16_t *x0, const uint16_t *i
             const int oa = (ta % 3) + 10 * ((ta / 3) % 3) + 100 * (ta / 9);
             const int ob = (tb % 3) + 10 * ((tb / 3) % 3) + 100 * (tb / 9);
 #pragma unroll
-            for (int t = 0; t < 8; t++) {
-                const int vox = (wave * 8 + t) * 16 + n;
+            for (int t = 0; t < TPW; t++) {
+                const int vox = (wave * TPW + t) * 16 + n;
                 const int u = (vox & 7) + 10 * ((vox >> 3) & 7) + 100 * (vox >> 6);
                 const uint2 xa = va ? *reinterpret_cast<const uint2 *>(&x0[(u + oa) * 4]) : make_uint2(0, 0);
                 const uint2 xb = vb ? *reinterpret_cast<const uint2 *>(&x0[(u + ob) * 4]) : make_uint2(0, 0);
@@ -113,8 +116,8 @@ __device__ __forceinline__ void conv_tiles(const uint16_t *x0, const uint16_t *i
         const i32x4 b = valid ? *reinterpret_cast<const i32x4 *>(&Wl[(wt * kC + n) * kC + 8 * h]) : zero;
         const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
 #pragma unroll
-        for (int t = 0; t < 8; t++) {
-            const int vox = (wave * 8 + t) * 16 + n;
+        for (int t = 0; t < TPW; t++) {
+            const int vox = (wave * TPW + t) * 16 + n;
             const int ux = (vox & 7) + dx - 1, uy = ((vox >> 3) & 7) + dy - 1, uz = (vox >> 6) + dz - 1;
             const bool inside = valid && (unsigned)ux < 8u && (unsigned)uy < 8u && (unsigned)uz < 8u;
             const i32x4 a = inside ? *reinterpret_cast<const i32x4 *>(&in[(ux + 8 * uy + 64 * uz) * kC + 8 * h])
@@ -126,26 +129,26 @@ __device__ __forceinline__ void conv_tiles(const uint16_t *x0, const uint16_t *i
 
 // forward through the 4 layers; leaves activations in L.act and returns, for the
 // lanes with output channel 0, the residual delta of their 4 voxels per tile
-template <int NACT>
-__device__ void refine_forward(RefineAct<NACT> &L, const RefineParams &P, int wave, int lane, f32x4 delta[8])
+template <int NACT, int TPW>
+__device__ void refine_forward(RefineAct<NACT> &L, const RefineParams &P, int wave, int lane, f32x4 delta[TPW])
 {
     const int kq = lane >> 4, n = lane & 15;
-    f32x4 acc[8];
+    f32x4 acc[TPW];
     for (int l = 0; l < kLayers; l++) {
         const uint16_t *in = l == 0 ? nullptr : L.act[(l - 1) % NACT];
-        conv_tiles(L.x0, in, l, P.Wf + (size_t)l * kTaps * kC * kC, false, wave, lane, acc);
+        conv_tiles<TPW>(L.x0, in, l, P.Wf + (size_t)l * kTaps * kC * kC, false, wave, lane, acc);
         const float b = P.bias[l * kC + n];
         if (l < kLayers - 1) {
 #pragma unroll
-            for (int t = 0; t < 8; t++)
+            for (int t = 0; t < TPW; t++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const int vox = (wave * TPW + t) * 16 + 4 * kq + r;
                     L.act[l % NACT][vox * kC + n] = to_bf16(fmaxf(acc[t][r] + b, 0.0f));
                 }
         } else {
 #pragma unroll
-            for (int t = 0; t < 8; t++)
+            for (int t = 0; t < TPW; t++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) delta[t][r] = acc[t][r] + b;
         }
@@ -170,23 +173,28 @@ __device__ void load_input(RefineAct<NACT> &L, const float *in)
     }
 }
 
+// The inference kernels' workgroups: kInferWaves waves, kInferTPW voxel tiles each
+constexpr int kInferWaves = 16;
+constexpr int kInferTPW = 32 / kInferWaves;
+
 // inference only: the refined F of each block
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_refine_infer(RefineArgs a)
+__global__ __launch_bounds__(kInferWaves * 64) void k_refine_infer(RefineArgs a)
 {
+    constexpr int TPW = kInferTPW;
     __shared__ RefineLdsInf L;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, n = lane & 15;
     for (int64_t blk = blockIdx.x; blk < a.n; blk += gridDim.x) {
         load_input(L, a.in + blk * 2000);
         __syncthreads();
-        f32x4 delta[8];
-        refine_forward(L, a.P, wave, lane, delta);
+        f32x4 delta[TPW];
+        refine_forward<2, TPW>(L, a.P, wave, lane, delta);
         if (n == 0) {
 #pragma unroll
-            for (int t = 0; t < 8; t++)
+            for (int t = 0; t < TPW; t++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const int vox = (wave * TPW + t) * 16 + 4 * kq + r;
                     a.out[blk * 512 + vox] = fminf(fmaxf(L.centre[vox] + delta[t][r], -1.0f), 1.0f);
                 }
         }
@@ -194,17 +202,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
 }
 
+// The training kernel's LDS (all activations and the gradients) allows one
+// workgroup per CU, so a block is split over 16 waves (4 per SIMD, 2 voxel tiles
+// and about 2 weight-gradient taps each) to hide its LDS and MFMA latencies.
+constexpr int kTrainWaves = 16;
+constexpr int kTrainTPW = 32 / kTrainWaves;
+
 template <bool TRAIN>
-__global__ __launch_bounds__(256) void k_refine(RefineArgs a)
+__global__ __launch_bounds__(kTrainWaves * 64) void k_refine(RefineArgs a)
 {
+    constexpr int TPW = kTrainTPW;
     __shared__ RefineLds L;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, n = lane & 15;
     for (int64_t blk = blockIdx.x; blk < a.n; blk += gridDim.x) {
         load_input(L, a.in + blk * 2000);
         __syncthreads();
-        f32x4 delta[8];
-        refine_forward(L, a.P, wave, lane, delta);
+        f32x4 delta[TPW];
+        refine_forward<3, TPW>(L, a.P, wave, lane, delta);
         // residual, clamp, loss gradient (lanes with output channel 0)
         float sq = 0.0f, cnt = 0.0f;
         if (TRAIN) {
@@ -216,10 +231,10 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
         }
         if (n == 0) {
 #pragma unroll
-            for (int t = 0; t < 8; t++)
+            for (int t = 0; t < TPW; t++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const int vox = (wave * TPW + t) * 16 + 4 * kq + r;
                     const float z = L.centre[vox] + delta[t][r];
                     const float Fo = fminf(fmaxf(z, -1.0f), 1.0f);
                     if (!TRAIN) {
@@ -238,8 +253,8 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
             __syncthreads();
             continue;
         }
-        // loss partial: reduce over the wave, then the 4 waves
-        __shared__ float red[2][4];
+        // loss partial: reduce over the wave, then over the waves in wave order
+        __shared__ float red[2][kTrainWaves];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
             sq += __shfl_xor(sq, o, 64);
@@ -248,8 +263,13 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
         if (lane == 0) { red[0][wave] = sq; red[1][wave] = cnt; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            a.loss_part[blk * 2] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-            a.loss_part[blk * 2 + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+            float s0 = 0.0f, s1 = 0.0f;
+            for (int w = 0; w < kTrainWaves; w++) {
+                s0 += red[0][w];
+                s1 += red[1][w];
+            }
+            a.loss_part[blk * 2] = s0;
+            a.loss_part[blk * 2 + 1] = s1;
         }
         float *gp = a.grad_part + blk * kNP;
         int cur = 0;
@@ -264,7 +284,7 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
             // weight gradient, taps split over the waves: per tap a 16 x 16 GEMM
             // over the 512 voxels (M = output channel, N = input channel)
             const uint16_t *X = l == 0 ? nullptr : L.act[l - 1];
-            for (int tap = wave; tap < kTaps; tap += 4) {
+            for (int tap = wave; tap < kTaps; tap += kTrainWaves) {
                 const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
                 f32x4 acc = {0.f, 0.f, 0.f, 0.f};
                 for (int ks = 0; ks < 32; ks++) {
@@ -291,15 +311,15 @@ __global__ __launch_bounds__(256) void k_refine(RefineArgs a)
             }
             if (l == 0) break;
             // data gradient into the previous layer's output, masked by its ReLU
-            f32x4 acc[8];
-            conv_tiles(L.x0, G, 1, a.P.Wt + (size_t)l * kTaps * kC * kC, true, wave, lane, acc);
+            f32x4 acc[TPW];
+            conv_tiles<TPW>(L.x0, G, 1, a.P.Wt + (size_t)l * kTaps * kC * kC, true, wave, lane, acc);
             uint16_t *Gn = L.grad[cur ^ 1];
             const uint16_t *A = L.act[l - 1];
 #pragma unroll
-            for (int t = 0; t < 8; t++)
+            for (int t = 0; t < TPW; t++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const int vox = (wave * TPW + t) * 16 + 4 * kq + r;
                     const bool on = from_bf16(A[vox * kC + n]) > 0.0f;
                     Gn[vox * kC + n] = on ? to_bf16(acc[t][r]) : (uint16_t)0;
                 }
@@ -428,8 +448,9 @@ __global__ void k_refine_gather(HashView h, const void *sdf, const void *w, cons
 // volume into LDS and the refined F goes to a side buffer (half precision,
 // indexed like the voxel block array) stamped with the frame number.
 template <int FMT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_refine_gated(RefineGateArgs a)
+__global__ __launch_bounds__(kInferWaves * 64) void k_refine_gated(RefineGateArgs a)
 {
+    constexpr int TPW = kInferTPW;
     using V = Vox<FMT>;
     __shared__ RefineLdsInf L;
     __shared__ int s_go;
@@ -474,14 +495,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 L.centre[(x - 1) + 8 * (y - 1) + 64 * (z - 1)] = F;
         }
         __syncthreads();
-        f32x4 delta[8];
-        refine_forward(L, a.P, wave, lane, delta);
+        f32x4 delta[TPW];
+        refine_forward<2, TPW>(L, a.P, wave, lane, delta);
         if (n == 0) {
 #pragma unroll
-            for (int t = 0; t < 8; t++)
+            for (int t = 0; t < TPW; t++)
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const int vox = (wave * 8 + t) * 16 + 4 * kq + r;
+                    const int vox = (wave * TPW + t) * 16 + 4 * kq + r;
                     const float Fo = fminf(fmaxf(L.centre[vox] + delta[t][r], -1.0f), 1.0f);
                     a.refined[(int64_t)ptr * kBlockVox + vox] = __float2half_rn(Fo);
                 }
@@ -494,17 +515,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 hipError_t launch_refine_gated(int fmt, const RefineGateArgs &a, int grid, hipStream_t st)
 {
     switch (fmt) {
-    case ITM_VOX_F32: launch_k(k_refine_gated<ITM_VOX_F32>, grid, 256, st, a); break;
-    case ITM_VOX_F16: launch_k(k_refine_gated<ITM_VOX_F16>, grid, 256, st, a); break;
-    default: launch_k(k_refine_gated<ITM_VOX_S16U8>, grid, 256, st, a); break;
+    case ITM_VOX_F32: launch_k(k_refine_gated<ITM_VOX_F32>, grid, kInferWaves * 64, st, a); break;
+    case ITM_VOX_F16: launch_k(k_refine_gated<ITM_VOX_F16>, grid, kInferWaves * 64, st, a); break;
+    default: launch_k(k_refine_gated<ITM_VOX_S16U8>, grid, kInferWaves * 64, st, a); break;
     }
     return hipGetLastError();
 }
 
 hipError_t launch_refine(const RefineArgs &a, bool train, int grid, hipStream_t st)
 {
-    if (train) k_refine<true><<<grid, 256, 0, st>>>(a);
-    else k_refine_infer<<<grid, 256, 0, st>>>(a);
+    if (train) k_refine<true><<<grid, kTrainWaves * 64, 0, st>>>(a);
+    else k_refine_infer<<<grid, kInferWaves * 64, 0, st>>>(a);
     return hipGetLastError();
 }
 
