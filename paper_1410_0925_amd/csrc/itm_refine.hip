@@ -275,11 +275,16 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_refine(RefineArgs a)
         int cur = 0;
         for (int l = kLayers - 1; l >= 0; l--) {
             const uint16_t *G = L.grad[cur];
-            // bias gradient: sum of the (bf16) output gradient over the voxels
-            if (threadIdx.x < kC) {
+            // bias gradient: sum of the (bf16) output gradient over the voxels, by
+            // the last wave (it has the fewest weight-gradient taps): lane = channel
+            // + 16 quarter, each quarter's 128 voxels in order, the quarters
+            // combined by a fixed butterfly
+            if (wave == kTrainWaves - 1) {
                 float s = 0.0f;
-                for (int v = 0; v < 512; v++) s += from_bf16(G[v * kC + threadIdx.x]);
-                gp[kNW + l * kC + threadIdx.x] = s;
+                for (int v = 128 * kq; v < 128 * (kq + 1); v++) s += from_bf16(G[v * kC + n]);
+                s += __shfl_xor(s, 16, 64);
+                s += __shfl_xor(s, 32, 64);
+                if (kq == 0) gp[kNW + l * kC + n] = s;
             }
             // weight gradient, taps split over the waves: per tap a 16 x 16 GEMM
             // over the 512 voxels (M = output channel, N = input channel)
