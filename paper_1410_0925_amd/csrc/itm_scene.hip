@@ -734,9 +734,10 @@ itm_status integrate_frame(itm_scene *sc, const float *depth, const uchar4 *rgbx
     }
     {
         ProfScope ps(sc, 1);
-        // enough waves for about one block each at VGA (5 workgroups per CU),
-        // more for tables that can list more blocks; a multiple of 8 workgroups
-        const int grid = (int)std::min<int64_t>(std::max<int64_t>(sc->num_cu * 5, sc->n_entries / 2048), 16384) / 8 * 8;
+        // 5 workgroups per CU: every wave resident at once (about one block each at
+        // VGA), looping over its share of the list when more are listed; a
+        // multiple of 8 workgroups
+        const int grid = (int)std::min<int64_t>((int64_t)sc->num_cu * 5, 16384) / 8 * 8;
         HIP_TRY(launch_integrate(sc->fmt, a, grid, sc->stream));
     }
     sc->fused_frame = sc->range_on ? sc->frame : -1;
