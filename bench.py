@@ -181,7 +181,7 @@ def track_leg(itm, torch, sc, st, depth, K, f, calls, cpu):
     return out
 
 
-def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True):
+def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True, tile_cap=0):
     """Colour voxels (section "Framework Flexibility"; the colour update of
     section "Integration"): the same frames fused with their registered colour
     images (itm_integrate_colour) and raycast with colour (itm_raycast_colour),
@@ -197,7 +197,7 @@ def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True
     crgb = torch.empty((H, W, 4), dtype=torch.uint8, device="cuda")
     sc = itm.Scene.from_params(st.params, fmt=fmt)
     sc.enable_colour()
-    sc.set_search_range(ranged)
+    sc.set_search_range(ranged, tile_cap)
     for f in range(warmup):
         sc.integrate_colour(depth[f], rgb[f], K, st.T_wc[f])
         sc.raycast_colour(K, st.T_wc[f], pts, nrm, crgb)
@@ -218,7 +218,8 @@ def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True
            "value": vis * 512 / wall, "unit": "voxels/s", "kernels": {}}
     if not events:
         return out
-    prof, rep = kernel_replay(itm, torch, st, depth, K, fmt, ranged, warmup, max(20, steps), rgb=rgb)
+    prof, rep = kernel_replay(itm, torch, st, depth, K, fmt, ranged, warmup, max(20, steps), rgb=rgb,
+                              tile_cap=tile_cap)
     for name in ("alloc", "integrate", "raycast"):
         ms, n = prof.get(name, (0.0, 0))
         if n == 0:
@@ -232,7 +233,7 @@ def colour_leg(itm, torch, st, depth, K, fmt, ranged, warmup, steps, events=True
     return out
 
 
-def kernel_replay(itm, torch, st, depth, K, fmt, ranged, first, n, rgb=None, pool=0):
+def kernel_replay(itm, torch, st, depth, K, fmt, ranged, first, n, rgb=None, pool=0, tile_cap=0):
     """Frames 0..first+n-1 on a fresh scene; frames first.. carry an event pair
     around every launch (on the scene's stream).  The launches are enqueued
     back to back and synchronised once at the end.  With rgb (colour images on
@@ -244,7 +245,7 @@ def kernel_replay(itm, torch, st, depth, K, fmt, ranged, first, n, rgb=None, poo
     sc = itm.Scene.from_params(st.params, fmt=fmt)
     if pool:
         sc.enable_swapping(pool, 0, 0)   # a device pool of `pool` blocks, no transfers
-    sc.set_search_range(ranged)
+    sc.set_search_range(ranged, tile_cap)
     if rgb is not None:
         sc.enable_colour()
 
@@ -334,6 +335,8 @@ def main():
     ap.add_argument("--colour-steps", type=int, default=None,
                     help="frames timed in the colour leg (default: the same frames as the main loop)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tile-capacity", type=int, default=0,
+                    help="expected-depth rectangles a 16x16 tile's bin holds (0: the library default)")
     ap.add_argument("--pool-blocks", type=int, default=0,
                     help="size the voxel block array to this many blocks (a device pool, "
                          "no transfers) instead of one block per hash entry")
@@ -375,7 +378,7 @@ def main():
     if args.pool_blocks:
         sc.enable_swapping(args.pool_blocks, 0, 0)
     ranged = args.search_range == "on"
-    sc.set_search_range(ranged)
+    sc.set_search_range(ranged, args.tile_capacity)
     for f in range(args.warmup):
         sc.integrate(depth[f], K, st.T_wc[f])
         sc.raycast(K, st.T_wc[f], pts, nrm)
@@ -411,7 +414,7 @@ def main():
     if not args.no_events:
         log("per-kernel events: replay of the timed frames")
         prof, rep = kernel_replay(itm, torch, st, depth, K, args.fmt, ranged, args.warmup,
-                                  max(20, args.steps), pool=args.pool_blocks)
+                                  max(20, args.steps), pool=args.pool_blocks, tile_cap=args.tile_capacity)
     kernels, best = {}, None
     for name in ("alloc", "integrate", "raycast"):
         ms, launches = prof.get(name, (0.0, 0))
@@ -462,7 +465,8 @@ def main():
                                f"{p['voxel_size']} m, mu {p['mu']} m, 2^{int(np.log2(p['n_buckets']))} "
                                f"buckets + 2^{int(np.log2(p['n_excess']))} excess, raycast {W}x{H}",
                    "storage": args.fmt, "search_range": "expected depths" if ranged else "z_near..z_far",
-                   "voxel_blocks": args.pool_blocks if args.pool_blocks else "one per hash entry"},
+                   "voxel_blocks": args.pool_blocks if args.pool_blocks else "one per hash entry",
+                   "tile_capacity": args.tile_capacity if args.tile_capacity else "library default"},
         "rays_per_s": rays / wall,
         "updated_voxels_per_s": upd_total / wall,
         "visible_blocks_per_frame": vis_total / args.steps,
@@ -483,7 +487,8 @@ def main():
     if not args.no_colour:
         log("colour voxels: fusion and raycast with colour")
         out["colour"] = colour_leg(itm, torch, st, depth, K, args.fmt, ranged, args.warmup,
-                                   min(args.colour_steps or args.steps, args.steps), not args.no_events)
+                                   min(args.colour_steps or args.steps, args.steps), not args.no_events,
+                                   args.tile_capacity)
     if not args.no_learned:
         log("learned form: refiner training steps and forward passes")
         out["learned"] = learned_leg(itm, torch)
