@@ -208,11 +208,38 @@ __global__ __launch_bounds__(kInferWaves * 64) void k_refine_infer(RefineArgs a)
 constexpr int kTrainWaves = 16;
 constexpr int kTrainTPW = 32 / kTrainWaves;
 
+// [channel][voxel] copies of a layer's output gradient and input for its weight
+// gradient (rows padded by 8 elements, so the 16-byte reads of lanes with
+// consecutive channels fall in different LDS banks)
+constexpr int kRowT = 512 + 8;
+
+// 8 bf16 of an x-row (x = 0..7) moved by s = -1, 0, +1 elements: element j of the
+// result is element j + s of the row, zero outside it
+__device__ __forceinline__ i32x4 shift_row(i32x4 r, int s)
+{
+    if (s == 0) return r;
+    i32x4 o;
+    if (s > 0) {
+        o[0] = (int)__builtin_amdgcn_alignbit((uint32_t)r[1], (uint32_t)r[0], 16);
+        o[1] = (int)__builtin_amdgcn_alignbit((uint32_t)r[2], (uint32_t)r[1], 16);
+        o[2] = (int)__builtin_amdgcn_alignbit((uint32_t)r[3], (uint32_t)r[2], 16);
+        o[3] = (int)__builtin_amdgcn_alignbit(0u, (uint32_t)r[3], 16);
+    } else {
+        o[0] = (int)__builtin_amdgcn_alignbit((uint32_t)r[0], 0u, 16);
+        o[1] = (int)__builtin_amdgcn_alignbit((uint32_t)r[1], (uint32_t)r[0], 16);
+        o[2] = (int)__builtin_amdgcn_alignbit((uint32_t)r[2], (uint32_t)r[1], 16);
+        o[3] = (int)__builtin_amdgcn_alignbit((uint32_t)r[3], (uint32_t)r[2], 16);
+    }
+    return o;
+}
+
 template <bool TRAIN>
 __global__ __launch_bounds__(kTrainWaves * 64) void k_refine(RefineArgs a)
 {
     constexpr int TPW = kTrainTPW;
     __shared__ RefineLds L;
+    __shared__ __attribute__((aligned(16))) uint16_t s_gT[kC * kRowT];   // output gradient, [channel][voxel]
+    __shared__ __attribute__((aligned(16))) uint16_t s_xT[kC * kRowT];   // layer input, [channel][voxel]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int kq = lane >> 4, n = lane & 15;
     for (int64_t blk = blockIdx.x; blk < a.n; blk += gridDim.x) {
@@ -289,30 +316,53 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_refine(RefineArgs a)
             // weight gradient, taps split over the waves: per tap a 16 x 16 GEMM
             // over the 512 voxels (M = output channel, N = input channel)
             const uint16_t *X = l == 0 ? nullptr : L.act[l - 1];
-            for (int tap = wave; tap < kTaps; tap += kTrainWaves) {
-                const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
-                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                for (int ks = 0; ks < 32; ks++) {
-                    bf16x4 av, bv;
-#pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        const int v = ks * 16 + 4 * kq + j;
-                        av[j] = (short)G[v * kC + n];
-                        const int x = v & 7, y = (v >> 3) & 7, z = v >> 6;
-                        uint16_t xv = 0;
-                        if (l == 0) {
-                            if (n < 4) xv = L.x0[((x + dx) + 10 * (y + dy) + 100 * (z + dz)) * 4 + n];
-                        } else {
-                            const int ux = x + dx - 1, uy = y + dy - 1, uz = z + dz - 1;
-                            if ((unsigned)ux < 8u && (unsigned)uy < 8u && (unsigned)uz < 8u)
-                                xv = X[(ux + 8 * uy + 64 * uz) * kC + n];
-                        }
-                        bv[j] = (short)xv;
-                    }
-                    acc = mfma16(av, bv, acc);
+            if (l > 0) {
+                // K = 32 voxels per step (4 x-rows); lane group kq takes row 4 ks + kq:
+                // A = 8 voxels of the gradient's channel row, B = the input row at the
+                // tap's (y, z) offset, moved by its x offset
+                for (int i = threadIdx.x; i < 512 * kC; i += blockDim.x) {
+                    s_gT[(i & 15) * kRowT + (i >> 4)] = G[i];
+                    s_xT[(i & 15) * kRowT + (i >> 4)] = X[i];
                 }
+                __syncthreads();
+                for (int tap = wave; tap < kTaps; tap += kTrainWaves) {
+                    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+                    for (int ks = 0; ks < 16; ks++) {
+                        const int row = 4 * ks + kq;   // y = row & 7, z = row >> 3
+                        const i32x4 av = *reinterpret_cast<const i32x4 *>(&s_gT[n * kRowT + 8 * row]);
+                        const int uy = (row & 7) + dy - 1, uz = (row >> 3) + dz - 1;
+                        i32x4 bv = {0, 0, 0, 0};
+                        if ((unsigned)uy < 8u && (unsigned)uz < 8u)
+                            bv = shift_row(*reinterpret_cast<const i32x4 *>(&s_xT[n * kRowT + 8 * (uy + 8 * uz)]),
+                                           dx - 1);
+                        acc = mfma32(av, bv, acc);
+                    }
 #pragma unroll
-                for (int r = 0; r < 4; r++) gp[((l * kTaps + tap) * kC + 4 * kq + r) * kC + n] = acc[r];
+                    for (int r = 0; r < 4; r++) gp[((l * kTaps + tap) * kC + 4 * kq + r) * kC + n] = acc[r];
+                }
+            } else {
+                // layer 0 reads the 10^3 input grid (4 stored channels): 2-byte gathers
+                for (int tap = wave; tap < kTaps; tap += kTrainWaves) {
+                    const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
+                    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                    for (int ks = 0; ks < 32; ks++) {
+                        bf16x4 av, bv;
+#pragma unroll
+                        for (int j = 0; j < 4; j++) {
+                            const int v = ks * 16 + 4 * kq + j;
+                            av[j] = (short)G[v * kC + n];
+                            const int x = v & 7, y = (v >> 3) & 7, z = v >> 6;
+                            uint16_t xv = 0;
+                            if (n < 4) xv = L.x0[((x + dx) + 10 * (y + dy) + 100 * (z + dz)) * 4 + n];
+                            bv[j] = (short)xv;
+                        }
+                        acc = mfma16(av, bv, acc);
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; r++) gp[((l * kTaps + tap) * kC + 4 * kq + r) * kC + n] = acc[r];
+                }
             }
             if (l == 0) break;
             // data gradient into the previous layer's output, masked by its ReLU
