@@ -233,6 +233,19 @@ __device__ __forceinline__ i32x4 shift_row(i32x4 r, int s)
     return o;
 }
 
+// elements d .. d + 7 (d = 0, 1, 2) of the 16 bf16 in (r0, r1)
+__device__ __forceinline__ i32x4 window8(i32x4 r0, i32x4 r1, int d)
+{
+    if (d == 0) return r0;
+    if (d == 2) return i32x4{r0[1], r0[2], r0[3], r1[0]};
+    i32x4 o;
+    o[0] = (int)__builtin_amdgcn_alignbit((uint32_t)r0[1], (uint32_t)r0[0], 16);
+    o[1] = (int)__builtin_amdgcn_alignbit((uint32_t)r0[2], (uint32_t)r0[1], 16);
+    o[2] = (int)__builtin_amdgcn_alignbit((uint32_t)r0[3], (uint32_t)r0[2], 16);
+    o[3] = (int)__builtin_amdgcn_alignbit((uint32_t)r1[0], (uint32_t)r0[3], 16);
+    return o;
+}
+
 template <bool TRAIN>
 __global__ __launch_bounds__(kTrainWaves * 64) void k_refine(RefineArgs a)
 {
@@ -343,22 +356,29 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_refine(RefineArgs a)
                     for (int r = 0; r < 4; r++) gp[((l * kTaps + tap) * kC + 4 * kq + r) * kC + n] = acc[r];
                 }
             } else {
-                // layer 0 reads the 10^3 input grid (4 stored channels): 2-byte gathers
+                // layer 0's input is the 10^3 grid (4 stored channels): its copy is
+                // [channel][z][y][x, padded to 16], and a tap's 8 inputs of a row are
+                // elements dx .. dx + 7 of it (two 16-byte reads); channels past the
+                // 4 stored read zeros
+                for (int i = threadIdx.x; i < 512 * kC; i += blockDim.x) s_gT[(i & 15) * kRowT + (i >> 4)] = G[i];
+                for (int i = threadIdx.x; i < 4 * 1000; i += blockDim.x) {
+                    const int u = i >> 2, c = i & 3;
+                    s_xT[((c * 10 + u / 100) * 10 + (u / 10) % 10) * 16 + u % 10] = L.x0[i];
+                }
+                __syncthreads();
                 for (int tap = wave; tap < kTaps; tap += kTrainWaves) {
                     const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;
                     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-                    for (int ks = 0; ks < 32; ks++) {
-                        bf16x4 av, bv;
-#pragma unroll
-                        for (int j = 0; j < 4; j++) {
-                            const int v = ks * 16 + 4 * kq + j;
-                            av[j] = (short)G[v * kC + n];
-                            const int x = v & 7, y = (v >> 3) & 7, z = v >> 6;
-                            uint16_t xv = 0;
-                            if (n < 4) xv = L.x0[((x + dx) + 10 * (y + dy) + 100 * (z + dz)) * 4 + n];
-                            bv[j] = (short)xv;
+#pragma unroll 4
+                    for (int ks = 0; ks < 16; ks++) {
+                        const int row = 4 * ks + kq;
+                        const i32x4 av = *reinterpret_cast<const i32x4 *>(&s_gT[n * kRowT + 8 * row]);
+                        i32x4 bv = {0, 0, 0, 0};
+                        if (n < 4) {
+                            const uint16_t *r = &s_xT[((n * 10 + (row >> 3) + dz) * 10 + (row & 7) + dy) * 16];
+                            bv = window8(*reinterpret_cast<const i32x4 *>(r), *reinterpret_cast<const i32x4 *>(r + 8), dx);
                         }
-                        acc = mfma16(av, bv, acc);
+                        acc = mfma32(av, bv, acc);
                     }
 #pragma unroll
                     for (int r = 0; r < 4; r++) gp[((l * kTaps + tap) * kC + 4 * kq + r) * kC + n] = acc[r];
