@@ -239,9 +239,10 @@ itm_status itm_export_colour(itm_scene *scene, uint8_t *rgbw, int64_t capacity, 
  * the storage form (section "Framework Flexibility"). */
 itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
 
-/* Per-kernel timing with HIP events recorded on the scene's stream around every
- * launch while enabled (toggling does not synchronise; events recorded while
- * enabled are kept until read).  Kernel ids: 0 allocation with the visible
+/* Per-kernel timing with a HIP event pair attached to every launch's dispatch
+ * (the kernel's own start and end) while enabled (toggling does not
+ * synchronise; events recorded while enabled are kept until read).  Kernel ids:
+ * 0 allocation with the visible
  * list (and, with the search range on, the expected-depth binning), 1
  * integration, 2 raycast (with the binning for a pose other than the last
  * frame's), 3 refiner gate, 4 tracker pairing and sums on the finest level,

@@ -127,6 +127,37 @@ def test_invalid_arguments():
         sc.integrate(d, (100.0, 100.0, 5.0, 5.0, 10, 10), T)
 
 
+def test_profile_counts_every_launch():
+    """Per-kernel timing: with profiling on, every launch of a frame carries its
+    own event pair on its dispatch and is counted once, with a positive time;
+    reading resets the counts, and launches with profiling off are not counted."""
+    itm, torch = gpu()
+    st = make_stream("tiny", n_frames=6)
+    print("case: tiny, profiled frames 1..5", flush=True)
+    sc = itm.Scene.from_params(st.params)
+    sc.set_search_range(True)
+    K = K_of(st)
+    depth = torch.from_numpy(st.depth).cuda()
+    pts = torch.empty((st.height, st.width, 4), dtype=torch.float32, device="cuda")
+    nrm = torch.empty_like(pts)
+    sc.integrate(depth[0], K, st.T_wc[0])
+    sc.raycast(K, st.T_wc[0], pts, nrm)
+    sc.profile(True)
+    for f in range(1, 6):
+        sc.integrate(depth[f], K, st.T_wc[f])
+        sc.raycast(K, st.T_wc[f], pts, nrm)
+    sc.profile(False)
+    r = sc.profile_read()
+    for k in ("alloc", "integrate", "raycast"):
+        ms, n = r[k]
+        assert n == 5, (k, n)
+        assert 0.0 < ms / n < 5.0, (k, ms)
+    assert all(r[k][1] == 0 for k in ("refine", "icp_fine", "icp_coarse", "icp_solve"))
+    sc.integrate(depth[0], K, st.T_wc[0])
+    assert all(n == 0 for _, n in sc.profile_read().values())
+    sc.close()
+
+
 def test_out_of_memory_is_a_status():
     """A table the device cannot hold (2^28 buckets: a 2.2 TB voxel block array)
     fails with ITM_ERR_OOM, frees what it had allocated, and leaves the device
