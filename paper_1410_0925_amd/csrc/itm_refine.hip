@@ -56,7 +56,8 @@ __device__ __forceinline__ f32x4 mfma32(i32x4 a, i32x4 b, f32x4 c)
 
 // LDS working set of one block (16-byte aligned rows: a lane's 8 channels are one
 // read).  Training keeps all three hidden activations for the backward pass
-// (92 KB: one workgroup per CU); inference alternates two (42 KB: three).
+// (92 KB, with the weight gradient's transposed copies 125 KB: one workgroup per
+// CU); inference alternates two (42 KB: two 16-wave workgroups per CU).
 template <int NACT>
 struct alignas(16) RefineAct {
     uint16_t x0[1000 * 4];          // network input, 10^3 grid, channels F, W/max_w, 0, 0
