@@ -244,8 +244,8 @@ itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
  * synchronise; events recorded while enabled are kept until read).  Kernel ids:
  * 0 allocation with the visible
  * list (and, with the search range on, the expected-depth binning), 1
- * integration, 2 raycast (with the binning for a pose other than the last
- * frame's), 3 refiner gate, 4 tracker pairing and sums on the finest level,
+ * integration, 2 raycast (not the re-binning a pose other than the last
+ * frame's takes first), 3 refiner gate, 4 tracker pairing and sums on the finest level,
  * 5 tracker pairing and sums on the coarser levels, 6 tracker solve and pose
  * update (every level). */
 #define ITM_KERNEL_COUNT 7
