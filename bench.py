@@ -157,15 +157,17 @@ def track_leg(itm, torch, sc, st, depth, K, f, calls, cpu):
     prof = sc.profile_read()
     ms_f, n_f = prof["icp_fine"]
     # algorithmic bytes of a finest-level launch: every depth pixel, the two
-    # reference maps at each pair, the workgroup sums
-    b = 4.0 * W * H + 32.0 * info["pairs"] + 4.0 * 29 * min((W * H + 255) // 256, 4 * 256)
+    # reference maps at each pair, the workgroup sums written and read back
+    # (one workgroup of 1024 threads per CU at most)
+    grid = min((W * H + 1023) // 1024, torch.cuda.get_device_properties(0).multi_processor_count)
+    b = 4.0 * W * H + 32.0 * info["pairs"] + 2 * 4.0 * 29 * grid
     avg = ms_f / max(n_f, 1)
     gbs = b / (avg * 1e-3) / 1e9
     err_t = float(np.abs(T[:3, 3] - st.T_wc[f][:3, 3]).max())
     out = {"frame": f, "ms_per_call": wall * 1e3 / calls, "calls": calls, "steps_per_call": info["steps"],
            "pairs_last": info["pairs"], "rms_last_m": info["rms"],
            "translation_error_m": err_t, "start_translation_error_m": float(np.abs(T_ref[:3, 3] - st.T_wc[f][:3, 3]).max()),
-           "kernels_us": {k: round(prof[k][0] / max(prof[k][1], 1) * 1e3, 3) for k in ("icp_fine", "icp_coarse", "icp_solve")},
+           "kernels_us": {k: round(prof[k][0] / max(prof[k][1], 1) * 1e3, 3) for k in ("icp_fine", "icp_coarse")},
            "icp_fine": {"bytes_per_launch": round(b), "achieved_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                         "bound": "hbm"}}
     if cpu:

@@ -245,10 +245,10 @@ itm_status itm_get_stats(itm_scene *scene, itm_stats *out);
  * 0 allocation with the visible
  * list (and, with the search range on, the expected-depth binning), 1
  * integration, 2 raycast (not the re-binning a pose other than the last
- * frame's takes first), 3 refiner gate, 4 tracker pairing and sums on the finest level,
- * 5 tracker pairing and sums on the coarser levels, 6 tracker solve and pose
- * update (every level). */
-#define ITM_KERNEL_COUNT 7
+ * frame's takes first), 3 refiner gate, 4 tracker step on the finest level
+ * (pairing, sums, and in the workgroup that finishes last the solve and pose
+ * update), 5 the same on the coarser levels. */
+#define ITM_KERNEL_COUNT 6
 itm_status itm_profile_enable(itm_scene *scene, int enable);
 /* Synchronises, then writes the summed milliseconds and launch counts per kernel
  * id since profiling was enabled, and resets them. */

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libitm.so")
 ITM_OK, ITM_ERR_ARG, ITM_ERR_OOM, ITM_ERR_HIP, ITM_ERR_STATE = 0, -1, -2, -3, -4
 ITM_VOX_F32, ITM_VOX_F16, ITM_VOX_S16U8 = 0, 1, 2
 FORMATS = {"f32": ITM_VOX_F32, "f16": ITM_VOX_F16, "s16u8": ITM_VOX_S16U8}
-KERNELS = ("alloc", "integrate", "raycast", "refine", "icp_fine", "icp_coarse", "icp_solve")
+KERNELS = ("alloc", "integrate", "raycast", "refine", "icp_fine", "icp_coarse")
 ITM_KERNEL_COUNT = len(KERNELS)
 
 

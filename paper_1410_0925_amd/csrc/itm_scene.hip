@@ -1247,24 +1247,24 @@ namespace {
 
 // where a tracker call keeps its per-workgroup sums, pose and flags
 struct TrackBufs {
-    float *part;       // [cap][kIcpSums]
+    float *part;       // [kIcpSums][cap]
     int32_t cap;       // most workgroups whose sums fit
     double *pose;      // [16] current estimate, then [32] the last system
-    int32_t *flags;    // [kTrackLevels] stop flags, then the step count
+    int32_t *flags;    // [kTrackLevels] stop flags, the step count, the finished-workgroup count
 };
 
 // the scene's tracker scratch, allocated on first use
 itm_status track_scratch(itm_scene *sc, TrackBufs &b)
 {
     if (!sc->trk_part) {
-        // one workgroup per CU: each thread takes several pixels of the finest
-        // level, so the per-thread reduction of the 29 sums is amortised
+        // one workgroup of 1024 threads per CU: a thread takes one or two pixels
+        // of the finest level, and the last workgroup has few partials to add
         sc->trk_part_cap = sc->num_cu;
         if (itm_status st = dev_alloc((void **)&sc->trk_part, sizeof(float) * kIcpSums * (size_t)sc->trk_part_cap,
                                       "tracker sums"))
             return st;
         if (itm_status st = dev_alloc((void **)&sc->trk_pose, sizeof(double) * 48, "tracker pose")) return st;
-        if (itm_status st = dev_alloc((void **)&sc->trk_flags, sizeof(int32_t) * (kTrackLevels + 1), "tracker flags"))
+        if (itm_status st = dev_alloc((void **)&sc->trk_flags, sizeof(int32_t) * (kTrackLevels + 2), "tracker flags"))
             return st;
     }
     b.part = sc->trk_part;
@@ -1318,14 +1318,20 @@ IcpArgs icp_args(const TrackBufs &b, const float *depth, const itm_intrinsics *K
     }
     a.dist = dist;
     a.pose = b.pose;
-    a.stop = nullptr;
+    a.stop = b.flags + level;   // cleared by k_track_init; set only by steps that update
+    a.steps = nullptr;
     a.part = b.part;
+    a.part_stride = b.cap;
+    a.done = reinterpret_cast<uint32_t *>(b.flags + kTrackLevels + 1);
+    a.sys = b.pose + 16;
+    a.min_inliers = 0;
+    a.update = 0;
     return a;
 }
 
 int icp_grid(const TrackBufs &b, const IcpArgs &a)
 {
-    return (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)a.wl * a.hl + 255) / 256, b.cap));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(((int64_t)a.wl * a.hl + kIcpThreads - 1) / kIcpThreads, b.cap));
 }
 
 PoseInit pose_init(const TrackBufs &b, const double *T)
@@ -1335,6 +1341,7 @@ PoseInit pose_init(const TrackBufs &b, const double *T)
     p.pose = b.pose;
     p.stop = b.flags;
     p.steps = b.flags + kTrackLevels;
+    p.done = reinterpret_cast<uint32_t *>(b.flags + kTrackLevels + 1);
     return p;
 }
 
@@ -1361,23 +1368,13 @@ itm_status track_run(itm_scene *sc, const TrackBufs &b, const float *depth, cons
     HIP_TRY(launch_track_init(pose_init(b, T_init), sc->stream));
     for (int l = p.n_levels - 1; l >= 0; l--) {
         IcpArgs a = icp_args(b, depth, K, l, ref_pts, ref_normals, T_ref, p.dist_thresh[l]);
-        a.stop = b.flags + l;
-        SolveArgs s;
-        s.part = b.part;
-        s.n_part = icp_grid(b, a);
-        s.pose = b.pose;
-        s.stop = b.flags + l;
-        s.steps = b.flags + kTrackLevels;
-        s.sys = b.pose + 16;
-        s.min_inliers = p.min_inliers;
-        s.update = 1;
+        a.steps = b.flags + kTrackLevels;
+        a.min_inliers = p.min_inliers;
+        a.update = 1;
+        const int grid = icp_grid(b, a);
         for (int it = 0; it < p.iters[l]; it++) {
-            {
-                ProfScope ps(sc, l == 0 ? 4 : 5);
-                HIP_TRY(launch_icp_sums(a, s.n_part, sc->stream));
-            }
-            ProfScope ps(sc, 6);
-            HIP_TRY(launch_icp_solve(s, sc->stream));
+            ProfScope ps(sc, l == 0 ? 4 : 5);
+            HIP_TRY(launch_icp_step(a, grid, sc->stream));
         }
     }
     double host[48];
@@ -1435,17 +1432,7 @@ itm_status itm_icp_system(itm_scene *sc, const float *depth, const itm_intrinsic
     if (itm_status st = track_scratch(sc, b)) return st;
     HIP_TRY(launch_track_init(pose_init(b, T), sc->stream));
     const IcpArgs a = icp_args(b, depth, K, level, ref_pts, ref_normals, T_ref, dist_thresh);
-    SolveArgs s;
-    s.part = b.part;
-    s.n_part = icp_grid(b, a);
-    s.pose = b.pose;
-    s.stop = nullptr;
-    s.steps = nullptr;
-    s.sys = b.pose + 16;
-    s.min_inliers = 0;
-    s.update = 0;
-    HIP_TRY(launch_icp_sums(a, s.n_part, sc->stream));
-    HIP_TRY(launch_icp_solve(s, sc->stream));
+    HIP_TRY(launch_icp_step(a, icp_grid(b, a), sc->stream));
     HIP_TRY(hipMemcpyAsync(sys, b.pose + 16, sizeof(double) * kIcpSums, hipMemcpyDeviceToHost, sc->stream));
     HIP_TRY(hipStreamSynchronize(sc->stream));
     return ITM_OK;
@@ -1463,7 +1450,7 @@ namespace {
 constexpr int kStaticParts = 1024;   // most sum workgroups (one per CU is used)
 constexpr size_t kScrPartBytes = sizeof(float) * kIcpSums * kStaticParts;
 constexpr size_t kScrPoseBytes = sizeof(double) * 48;
-constexpr size_t kScrFlagBytes = sizeof(int32_t) * (kTrackLevels + 1);
+constexpr size_t kScrFlagBytes = sizeof(int32_t) * (kTrackLevels + 2);
 constexpr size_t kScratchBytes = (kScrPartBytes + kScrPoseBytes + kScrFlagBytes + 255) / 256 * 256;
 static_assert(kScrPartBytes % 8 == 0, "the pose must stay 8-byte aligned");
 
@@ -1509,8 +1496,8 @@ itm_status itm_track_noalloc(itm_scene *sc, const float *depth, const itm_intrin
     if (dev != sc->device)
         return fail(ITM_ERR_ARG, "the scene lives on device %d but device %d is current", sc->device, dev);
     if (sc->num_cu > kStaticParts)
-        return fail(ITM_ERR_ARG, "%d compute units need more than the %d sum rows of the static scratch", sc->num_cu,
-                    kStaticParts);
+        return fail(ITM_ERR_ARG, "%d compute units need more workgroup partials than the %d of the static scratch",
+                    sc->num_cu, kStaticParts);
     void *base = nullptr;
     if (itm_status st = static_scratch(&base)) return st;
     TrackBufs b;

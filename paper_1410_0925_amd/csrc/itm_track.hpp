@@ -7,13 +7,15 @@ namespace itm {
 
 // depth tracker (itm_track.hip)
 constexpr int kTrackLevels = 4;
-constexpr int kIcpSums = 29;   // upper triangle of A (21), g (6), sum d^2, pairs
+constexpr int kIcpSums = 29;      // upper triangle of A (21), g (6), sum d^2, pairs
+constexpr int kIcpThreads = 1024; // threads per workgroup of k_icp_step
 
 struct PoseInit {
     double T[16];        // the pose to start from (row-major camera -> world)
     double *pose;        // device double[16]
     int32_t *stop;       // device int32[kTrackLevels], cleared
     int32_t *steps;      // device int32, cleared
+    uint32_t *done;      // device uint32, cleared
 };
 
 struct IcpArgs {
@@ -25,24 +27,18 @@ struct IcpArgs {
     const float4 *V, *N;         // reference maps, world frame, w > 0 = hit
     float Rr[9], tr[3];          // reference pose (camera -> world)
     float dist;                  // pairing distance
-    const double *pose;          // current estimate, device double[16]
-    const int32_t *stop;         // the level's stop flag, or nullptr
-    float *part;                 // per-workgroup sums [grid][kIcpSums]
-};
-
-struct SolveArgs {
-    const float *part;
-    int32_t n_part;
-    double *pose;
-    int32_t *stop;               // nullptr with update == 0
-    int32_t *steps;
-    double *sys;                 // out: device double[kIcpSums]
-    int32_t min_inliers;
+    double *pose;                // current estimate, device double[16]; moved by the step
+    int32_t *stop;               // the level's stop flag (read even when update == 0)
+    int32_t *steps;              // steps taken, or nullptr (then update == 0)
+    float *part;                 // per-workgroup sums, sum k of workgroup j at part[k * part_stride + j]
+    int32_t part_stride;         // >= the grid
+    uint32_t *done;              // workgroups finished; zero between launches
+    double *sys;                 // out: device double[kIcpSums], the summed system
+    int32_t min_inliers;         // fewer pairs stop the level
     int32_t update;              // 0: sums only
 };
 
 hipError_t launch_track_init(const PoseInit &a, hipStream_t st);
-hipError_t launch_icp_sums(const IcpArgs &a, int grid, hipStream_t st);
-hipError_t launch_icp_solve(const SolveArgs &a, hipStream_t st);
+hipError_t launch_icp_step(const IcpArgs &a, int grid, hipStream_t st);
 
 }  // namespace itm

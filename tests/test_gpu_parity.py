@@ -152,7 +152,7 @@ def test_profile_counts_every_launch():
         ms, n = r[k]
         assert n == 5, (k, n)
         assert 0.0 < ms / n < 5.0, (k, ms)
-    assert all(r[k][1] == 0 for k in ("refine", "icp_fine", "icp_coarse", "icp_solve"))
+    assert all(r[k][1] == 0 for k in ("refine", "icp_fine", "icp_coarse"))
     sc.integrate(depth[0], K, st.T_wc[0])
     assert all(n == 0 for _, n in sc.profile_read().values())
     sc.close()
