@@ -105,8 +105,8 @@ struct itm_scene {
     // depth tracker scratch, allocated on first use
     float *trk_part = nullptr;        // [trk_part_cap][kIcpSums] per-workgroup sums
     int32_t trk_part_cap = 0;
-    double *trk_pose = nullptr;       // [16] current estimate, then [32] the last system
-    int32_t *trk_flags = nullptr;     // [kTrackLevels] stop flags, then the step count
+    double *trk_pose = nullptr;       // [16] current estimate, [32] the last system, then the flags
+                                      // (TrackBufs::flags), read back by one copy
 
     uchar4 *clr = nullptr;            // [vba_cap][512] colour voxels, allocated on enable
 
@@ -197,7 +197,6 @@ void release(itm_scene *sc)
     (void)hipFree(sc->stamp);
     (void)hipFree(sc->trk_part);
     (void)hipFree(sc->trk_pose);
-    (void)hipFree(sc->trk_flags);
     (void)hipFree(sc->clr);
     for (void *p : {(void *)sc->blk, (void *)sc->onhost, (void *)sc->pool_stack, (void *)sc->pool_top,
                     (void *)sc->pool_noblock, (void *)sc->swap_in_list, (void *)sc->swap_out_list,
@@ -1250,8 +1249,11 @@ struct TrackBufs {
     float *part;       // [kIcpSums][cap]
     int32_t cap;       // most workgroups whose sums fit
     double *pose;      // [16] current estimate, then [32] the last system
-    int32_t *flags;    // [kTrackLevels] stop flags, the step count, the finished-workgroup count
+    int32_t *flags;    // [kTrackLevels] stop flags, the step count, the finished-workgroup count;
+                       // right after the pose's 48 doubles, so that one copy reads both back
 };
+
+constexpr size_t kTrackStateBytes = sizeof(double) * 48 + sizeof(int32_t) * (kTrackLevels + 2);
 
 // the scene's tracker scratch, allocated on first use
 itm_status track_scratch(itm_scene *sc, TrackBufs &b)
@@ -1263,14 +1265,12 @@ itm_status track_scratch(itm_scene *sc, TrackBufs &b)
         if (itm_status st = dev_alloc((void **)&sc->trk_part, sizeof(float) * kIcpSums * (size_t)sc->trk_part_cap,
                                       "tracker sums"))
             return st;
-        if (itm_status st = dev_alloc((void **)&sc->trk_pose, sizeof(double) * 48, "tracker pose")) return st;
-        if (itm_status st = dev_alloc((void **)&sc->trk_flags, sizeof(int32_t) * (kTrackLevels + 2), "tracker flags"))
-            return st;
+        if (itm_status st = dev_alloc((void **)&sc->trk_pose, kTrackStateBytes, "tracker pose and flags")) return st;
     }
     b.part = sc->trk_part;
     b.cap = sc->trk_part_cap;
     b.pose = sc->trk_pose;
-    b.flags = sc->trk_flags;
+    b.flags = reinterpret_cast<int32_t *>(sc->trk_pose + 48);
     return ITM_OK;
 }
 
@@ -1377,11 +1377,13 @@ itm_status track_run(itm_scene *sc, const TrackBufs &b, const float *depth, cons
             HIP_TRY(launch_icp_step(a, grid, sc->stream));
         }
     }
-    double host[48];
-    int32_t flags[kTrackLevels + 1];
-    HIP_TRY(hipMemcpyAsync(host, b.pose, sizeof host, hipMemcpyDeviceToHost, sc->stream));
-    HIP_TRY(hipMemcpyAsync(flags, b.flags, sizeof flags, hipMemcpyDeviceToHost, sc->stream));
+    alignas(8) unsigned char state[kTrackStateBytes];   // the pose, the last system and the flags
+    HIP_TRY(hipMemcpyAsync(state, b.pose, sizeof state, hipMemcpyDeviceToHost, sc->stream));
     HIP_TRY(hipStreamSynchronize(sc->stream));
+    double host[48];
+    int32_t flags[kTrackLevels + 2];
+    std::memcpy(host, state, sizeof host);
+    std::memcpy(flags, state + sizeof host, sizeof flags);
     std::memcpy(T_out, host, sizeof(double) * 16);
     if (info) {
         // the last system evaluated (zeros when no step ran)
@@ -1449,9 +1451,7 @@ namespace {
 
 constexpr int kStaticParts = 1024;   // most sum workgroups (one per CU is used)
 constexpr size_t kScrPartBytes = sizeof(float) * kIcpSums * kStaticParts;
-constexpr size_t kScrPoseBytes = sizeof(double) * 48;
-constexpr size_t kScrFlagBytes = sizeof(int32_t) * (kTrackLevels + 2);
-constexpr size_t kScratchBytes = (kScrPartBytes + kScrPoseBytes + kScrFlagBytes + 255) / 256 * 256;
+constexpr size_t kScratchBytes = (kScrPartBytes + kTrackStateBytes + 255) / 256 * 256;
 static_assert(kScrPartBytes % 8 == 0, "the pose must stay 8-byte aligned");
 
 // Each GPU the library runs on holds its own copy until the process ends; in
@@ -1504,7 +1504,7 @@ itm_status itm_track_noalloc(itm_scene *sc, const float *depth, const itm_intrin
     b.part = reinterpret_cast<float *>(base);
     b.cap = sc->num_cu;   // the grid of itm_track, so both give the same sums bit for bit
     b.pose = reinterpret_cast<double *>(static_cast<unsigned char *>(base) + kScrPartBytes);
-    b.flags = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(base) + kScrPartBytes + kScrPoseBytes);
+    b.flags = reinterpret_cast<int32_t *>(b.pose + 48);
     return track_run(sc, b, depth, K, ref_pts, ref_normals, T_ref, T_init, params, T_out, info);
 }
 }  // extern "C"
