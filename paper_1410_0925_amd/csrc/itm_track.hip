@@ -198,10 +198,9 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp_step(IcpArgs a)
 {
     const int n_px = a.wl * a.hl, stride = gridDim.x * kIcpThreads;
     int i = blockIdx.x * kIcpThreads + threadIdx.x;
-    // the first pixel's depth, the stop flag and the pose are all requested
-    // before any of them is waited for
-    // (every read below is of a valid address, clamped rather than branched
-    // around, so that the compiler issues them together and waits once)
+    // The first pixel's depth, the stop flag and the pose are all requested
+    // before any of them is waited for.  Every depth read is of a valid address,
+    // clamped rather than branched around, so that the compiler issues it early.
     float d = level_depth(a, min(i, n_px - 1));
     double T0[12];
 #pragma unroll
@@ -259,7 +258,8 @@ __global__ __launch_bounds__(kIcpThreads) void k_icp_step(IcpArgs a)
 
     // The last workgroup: every other partial was complete before its ticket,
     // and it reads them with device-scope loads.
-    if (threadIdx.x == 0) __hip_atomic_store(a.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // for the next launch
+    if (threadIdx.x == 0)   // the count starts from zero at the next launch
+        __hip_atomic_store(a.done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // Thread (k, l) adds partials l, l + 32, ... of sum k in float64, eight loads
     // in flight at a time, and the 32 threads of a sum are added by a fixed
     // butterfly -- the same order at every call.
