@@ -413,7 +413,11 @@ class Refiner:
             itm_refiner_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter exit this module's names may already be None: the
+        # process's end then releases the device memory
+        if itm_refiner_destroy is not None and _lib is not None:
+            self.close()
 
     def _sync_stream(self):
         _check(lib().itm_refiner_set_stream(self.h, _stream()))
@@ -465,7 +469,11 @@ class Scene:
             itm_scene_destroy(self.h)
             self.h = None
 
-    __del__ = close
+    def __del__(self):
+        # at interpreter exit this module's names may already be None: the
+        # process's end then releases the device memory
+        if itm_scene_destroy is not None and _lib is not None:
+            self.close()
 
     def __enter__(self):
         return self
