@@ -372,10 +372,20 @@ struct RefineGateArgs {
 
 hipError_t launch_refine(const RefineArgs &a, bool train, int grid, hipStream_t st);
 hipError_t launch_refine_gated(int fmt, const RefineGateArgs &a, int grid, hipStream_t st);
+// one Adam step (beta 0.9, 0.999, eps 1e-8) on the float32 master weights,
+// applied by the gradient reduction where it is given
+struct AdamStep {
+    float *master, *m, *v;   // [kRefineParams] each
+    uint16_t *Wf, *Wt;       // bf16 copies of the weights, forward and transposed
+    float *bias;             // float32 copy of the biases
+    float lr;
+    int step;                // 1 at the first step
+};
+
+// grad, loss: where the mean gradient and the loss go; adam: nullptr for the
+// gradient alone
 hipError_t launch_refine_reduce(const float *grad_part, const float *loss_part, int64_t n, float *grad,
-                                float *loss, hipStream_t st);
-hipError_t launch_refine_adam(float *master, float *m, float *v, const float *grad, uint16_t *Wf, uint16_t *Wt,
-                              float *bias, float lr, int step, hipStream_t st);
+                                float *loss, const AdamStep *adam, hipStream_t st);
 hipError_t launch_refine_cast(const float *master, uint16_t *Wf, uint16_t *Wt, float *bias, hipStream_t st);
 hipError_t launch_refine_gather(int fmt, const HashView &h, const void *sdf, const void *w, const int32_t *coords,
                                 int64_t n, float inv_max_w, float *out, hipStream_t st);

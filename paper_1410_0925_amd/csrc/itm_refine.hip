@@ -17,8 +17,8 @@
 // convolution of the output gradient with the tap-flipped, channel-transposed
 // kernel; the weight gradient is, per tap, a 16 x 16 GEMM over the 512 voxels.
 // Each block writes its gradient to its own row of a partial buffer; a second
-// kernel sums the rows in a fixed order (deterministic), and Adam updates the
-// float32 master weights and re-rounds the bf16 copies.
+// kernel sums the rows in a fixed order (deterministic) and, in a training step,
+// applies Adam to the float32 master weights and re-rounds the bf16 copies.
 #include <algorithm>
 
 #include "itm_internal.hpp"
@@ -410,25 +410,63 @@ __global__ __launch_bounds__(kTrainWaves * 64) void k_refine(RefineArgs a)
 // voxels.  A workgroup takes 64 parameters; its 4 waves each add a contiguous
 // quarter of the block rows (in row order), and the quarters are added in a fixed
 // order, so the result does not depend on scheduling.
+// Adam's constants for one step (bias corrections from the step count)
+struct AdamConst {
+    float lr, b1, b2, eps, c1, c2;
+};
+
+// Adam on float32 master weight p (value w0, moments m0 and v0) with gradient
+// g, then its bf16 copies
+__device__ __forceinline__ void adam_update(const AdamStep &ad, const AdamConst &k, int p, float g, float w0,
+                                            float m0, float v0)
+{
+    const float mm = k.b1 * m0 + (1.0f - k.b1) * g;
+    const float vv = k.b2 * v0 + (1.0f - k.b2) * g * g;
+    ad.m[p] = mm;
+    ad.v[p] = vv;
+    const float w = w0 - k.lr * (mm / k.c1) / (sqrtf(vv / k.c2) + k.eps);
+    ad.master[p] = w;
+    if (p < kNW) {
+        ad.Wf[p] = to_bf16(w);
+        const int ci = p % kC, co = (p / kC) % kC, lt = p / (kC * kC);
+        ad.Wt[(lt * kC + ci) * kC + co] = to_bf16(w);
+    } else {
+        ad.bias[p - kNW] = w;
+    }
+}
+
+// The mean gradient (and with ADAM the step it drives): per parameter, the
+// partial rows added in a fixed order, divided by the count of masked voxels
+template <bool ADAM>
 __global__ __launch_bounds__(256) void k_refine_reduce(const float *grad_part, const float *loss_part, int64_t n,
-                                                       float *grad, float *loss)
+                                                       float *grad, float *loss, AdamStep ad, AdamConst k)
 {
     __shared__ float part[4][64];
     __shared__ float s_inv;
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int p = blockIdx.x * 64 + lane;
     const int64_t r0 = n * q / 4, r1 = n * (q + 1) / 4;
-    // the quarter's rows added in row order, eight loads in flight ahead of the
-    // additions
+    // the weight and its moments are read first, so that their round trip
+    // overlaps the partial rows'
+    float w0 = 0.0f, m0 = 0.0f, v0 = 0.0f;
+    if (ADAM && q == 0 && p < kNP) {
+        w0 = ad.master[p];
+        m0 = ad.m[p];
+        v0 = ad.v[p];
+    }
+    // the quarter's rows added in row order, sixteen loads in flight ahead of
+    // the additions (the scheduling barrier keeps the compiler from moving the
+    // first additions, and so their waits, between the loads)
     float acc = 0.0f;
     if (p < kNP) {
         int64_t b = r0;
-        for (; b + 8 <= r1; b += 8) {
-            float v[8];
+        for (; b + 16 <= r1; b += 16) {
+            float v[16];
 #pragma unroll
-            for (int k = 0; k < 8; k++) v[k] = grad_part[(b + k) * kNP + p];
+            for (int j = 0; j < 16; j++) v[j] = grad_part[(b + j) * kNP + p];
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int k = 0; k < 8; k++) acc += v[k];
+            for (int j = 0; j < 16; j++) acc += v[j];
         }
         for (; b < r1; b++) acc += grad_part[b * kNP + p];
     }
@@ -452,29 +490,10 @@ __global__ __launch_bounds__(256) void k_refine_reduce(const float *grad_part, c
         }
     }
     __syncthreads();
-    if (q == 0 && p < kNP) grad[p] = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) * s_inv;
-}
-
-// Adam on float32 master weights, then the two bf16 copies
-__global__ void k_refine_adam(float *master, float *m, float *v, const float *grad, uint16_t *Wf,
-                              uint16_t *Wt, float *bias, float lr, float b1, float b2, float eps,
-                              float c1, float c2)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= kNP) return;
-    const float g = grad[p];
-    const float mm = b1 * m[p] + (1.0f - b1) * g;
-    const float vv = b2 * v[p] + (1.0f - b2) * g * g;
-    m[p] = mm;
-    v[p] = vv;
-    const float w = master[p] - lr * (mm / c1) / (sqrtf(vv / c2) + eps);
-    master[p] = w;
-    if (p < kNW) {
-        Wf[p] = to_bf16(w);
-        const int ci = p % kC, co = (p / kC) % kC, lt = p / (kC * kC);
-        Wt[(lt * kC + ci) * kC + co] = to_bf16(w);
-    } else {
-        bias[p - kNW] = w;
+    if (q == 0 && p < kNP) {
+        const float g = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) * s_inv;
+        grad[p] = g;
+        if (ADAM) adam_update(ad, k, p, g, w0, m0, v0);
     }
 }
 
@@ -606,18 +625,21 @@ hipError_t launch_refine(const RefineArgs &a, bool train, int grid, hipStream_t 
 }
 
 hipError_t launch_refine_reduce(const float *grad_part, const float *loss_part, int64_t n, float *grad,
-                                float *loss, hipStream_t st)
+                                float *loss, const AdamStep *adam, hipStream_t st)
 {
-    k_refine_reduce<<<(kNP + 63) / 64, 256, 0, st>>>(grad_part, loss_part, n, grad, loss);
-    return hipGetLastError();
-}
-
-hipError_t launch_refine_adam(float *master, float *m, float *v, const float *grad, uint16_t *Wf, uint16_t *Wt,
-                              float *bias, float lr, int step, hipStream_t st)
-{
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
-    k_refine_adam<<<(kNP + 255) / 256, 256, 0, st>>>(master, m, v, grad, Wf, Wt, bias, lr, b1, b2, 1e-8f, c1, c2);
+    const int grid = (kNP + 63) / 64;
+    if (adam) {
+        AdamConst k;
+        k.lr = adam->lr;
+        k.b1 = 0.9f;
+        k.b2 = 0.999f;
+        k.eps = 1e-8f;
+        k.c1 = 1.0f - powf(k.b1, (float)adam->step);
+        k.c2 = 1.0f - powf(k.b2, (float)adam->step);
+        k_refine_reduce<true><<<grid, 256, 0, st>>>(grad_part, loss_part, n, grad, loss, *adam, k);
+    } else {
+        k_refine_reduce<false><<<grid, 256, 0, st>>>(grad_part, loss_part, n, grad, loss, AdamStep{}, AdamConst{});
+    }
     return hipGetLastError();
 }
 

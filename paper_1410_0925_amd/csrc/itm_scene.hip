@@ -1604,8 +1604,10 @@ itm_status itm_refiner_forward(itm_refiner *r, const float *in, int64_t n, float
     return ITM_OK;
 }
 
+// the mean gradient into grad and the loss into loss (device pointers), with
+// one Adam step in the same launch where adam is given
 static itm_status refiner_grad(itm_refiner *r, const float *in, const float *target, const uint8_t *mask,
-                               int64_t n)
+                               int64_t n, float *grad, float *loss, const AdamStep *adam)
 {
     if (!r || n <= 0 || !in || !target || !mask) return fail(ITM_ERR_ARG, "bad refiner gradient arguments");
     if (n > r->part_cap) {
@@ -1629,28 +1631,31 @@ static itm_status refiner_grad(itm_refiner *r, const float *in, const float *tar
     a.grad_part = r->grad_part;
     a.loss_part = r->loss_part;
     HIP_TRY(launch_refine(a, true, (int)std::min<int64_t>(n, (int64_t)r->num_cu * 2), r->stream));
-    HIP_TRY(launch_refine_reduce(r->grad_part, r->loss_part, n, r->grad, r->loss, r->stream));
+    HIP_TRY(launch_refine_reduce(r->grad_part, r->loss_part, n, grad, loss, adam, r->stream));
     return ITM_OK;
 }
 
 itm_status itm_refiner_gradient(itm_refiner *r, const float *in, const float *target, const uint8_t *mask,
                                 int64_t n, float *grad, float *loss)
 {
-    if (itm_status st = refiner_grad(r, in, target, mask, n)) return st;
-    if (grad)
-        HIP_TRY(hipMemcpyAsync(grad, r->grad, sizeof(float) * kRefineParams, hipMemcpyDeviceToDevice, r->stream));
-    if (loss) HIP_TRY(hipMemcpyAsync(loss, r->loss, sizeof(float), hipMemcpyDeviceToDevice, r->stream));
-    return ITM_OK;
+    return refiner_grad(r, in, target, mask, n, grad ? grad : r->grad, loss ? loss : r->loss, nullptr);
 }
 
 itm_status itm_refiner_train_step(itm_refiner *r, const float *in, const float *target, const uint8_t *mask,
                                   int64_t n, float lr, float *loss)
 {
     if (!(lr > 0)) return fail(ITM_ERR_ARG, "learning rate must be > 0");
-    if (itm_status st = refiner_grad(r, in, target, mask, n)) return st;
+    AdamStep ad;
+    ad.master = r->master;
+    ad.m = r->m;
+    ad.v = r->v;
+    ad.Wf = r->Wf;
+    ad.Wt = r->Wt;
+    ad.bias = r->bias;
+    ad.lr = lr;
+    ad.step = r->step + 1;
+    if (itm_status st = refiner_grad(r, in, target, mask, n, r->grad, loss ? loss : r->loss, &ad)) return st;
     r->step++;
-    HIP_TRY(launch_refine_adam(r->master, r->m, r->v, r->grad, r->Wf, r->Wt, r->bias, lr, r->step, r->stream));
-    if (loss) HIP_TRY(hipMemcpyAsync(loss, r->loss, sizeof(float), hipMemcpyDeviceToDevice, r->stream));
     return ITM_OK;
 }
 
