@@ -321,13 +321,17 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
             slot4[q] = set_claim(s_k, pack_key(cx[q], cy[q], cz[q]), owner);
             if (owner || slot4[q] < 0) probe |= 1u << q;
         }
+        // Every lane reads its four buckets (any block's bucket is a valid
+        // address; a lane that does not probe a block reads a line its owner
+        // reads too) and keeps the records it probes: read under a branch, the
+        // first record was waited for before the other three were issued.
         ulonglong2 k2[4];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            k2[q] = make_ulonglong2(0ull, 0ull);   // no valid key is 0
-            if (probe & (1u << q))
-                k2[q] = *reinterpret_cast<const ulonglong2 *>(a.h.buckets[hash_index(cx[q], cy[q], cz[q], a.h.mask)].key);
-        }
+        for (int q = 0; q < 4; q++)
+            k2[q] = *reinterpret_cast<const ulonglong2 *>(a.h.buckets[hash_index(cx[q], cy[q], cz[q], a.h.mask)].key);
+#pragma unroll
+        for (int q = 0; q < 4; q++)
+            if (!(probe & (1u << q))) k2[q] = make_ulonglong2(0ull, 0ull);   // no valid key is 0
         int32_t e4[4];
         uint32_t slow = 0;
 #pragma unroll
@@ -349,18 +353,27 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
             for (int r = 0; r < 4; r++)
                 if (r == q) e4[r] = e;
         }
+        // The batch's stamp exchanges, all issued before any is waited for (the
+        // results are opaque to the compiler until all four are out, for the
+        // reason above): the first workgroup to stamp a block lists it.
+        uint32_t old4[4];
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            old4[q] = a.stamp_now;
+            if ((probe & (1u << q)) && e4[q] >= 0) old4[q] = atomicExch(&a.stamp[e4[q]], a.stamp_now);
+        }
+        asm volatile("" : "+v"(old4[0]), "+v"(old4[1]), "+v"(old4[2]), "+v"(old4[3]));
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             if (!(probe & (1u << q))) continue;
             const int32_t e = e4[q];
             if (slot4[q] >= 0) {
-                // stamped at once, while other lanes still probe: the first
-                // workgroup to stamp the block lists it; -1 (dropped, or listed
-                // by another workgroup) leaves the slot out of the list
-                const bool first = e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now;
+                // stamped while other lanes still probe; -1 (dropped, or listed by
+                // another workgroup) leaves the slot out of the list
+                const bool first = e >= 0 && old4[q] != a.stamp_now;
                 s_e[slot4[q]] = first ? e : -1;
                 if (first) device_block(a, e);
-            } else if (e >= 0 && atomicExch(&a.stamp[e], a.stamp_now) != a.stamp_now) {
+            } else if (e >= 0 && old4[q] != a.stamp_now) {
                 // the workgroup's set is full: list the block on its own; its
                 // expected-depth rectangle is not binned, so the frame's bins are
                 // marked incomplete (every tile then computes its range exactly
