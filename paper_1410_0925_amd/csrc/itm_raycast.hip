@@ -91,8 +91,12 @@ struct Cube {
                (lz >> 3) >= bz0 && (hz >> 3) <= bz1;
     }
 
-    // every block is probed (the march's cached block is not reused: keeping it
-    // live costs registers)
+    // Every block is probed (the march's cached block is not reused: keeping it
+    // live costs registers).  The 8 buckets are read together -- every block's
+    // bucket is a valid address, and the records of blocks the region does not
+    // reach are dropped -- then matched; a block whose bucket holds two other
+    // keys walks the excess chain.  (Read under a branch each, the buckets were
+    // waited for one at a time.)
     template <bool REF>
     __device__ void fetch(const HashView &h, const VoxSrc<FMT, REF> &src, int lx, int ly, int lz, int hx, int hy,
                           int hz)
@@ -100,17 +104,67 @@ struct Cube {
         bx0 = lx >> 3; by0 = ly >> 3; bz0 = lz >> 3;
         bx1 = hx >> 3; by1 = hy >> 3; bz1 = hz >> 3;
         const bool sx = bx1 != bx0, sy = by1 != by0, sz = bz1 != bz0;
+        ulonglong2 k2[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            const int kx = (c & 1) ? bx1 : bx0, ky = (c & 2) ? by1 : by0, kz = (c & 4) ? bz1 : bz0;
+            k2[c] = *reinterpret_cast<const ulonglong2 *>(h.buckets[hash_index(kx, ky, kz, h.mask)].key);
+        }
+        // (opaque from here: the compiler would otherwise move the first
+        // block's read into the key-range test's branch and split it there)
+#pragma unroll
+        for (int c = 0; c < 8; c++) asm volatile("" : "+v"(k2[c].x), "+v"(k2[c].y));
+        uint32_t slow = 0;
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
             const bool need = (!dx || sx) && (!dy || sy) && (!dz || sz);
             const int kx = dx ? bx1 : bx0, ky = dy ? by1 : by0, kz = dz ? bz1 : bz0;
-            p[c] = need ? block_of(h, find_block_direct(h, kx, ky, kz)) : -1;
+            const unsigned long long key = pack_key(kx, ky, kz);
+            const int32_t bi = 2 * (int32_t)hash_index(kx, ky, kz, h.mask);
+            int32_t e = -1;
+            if (need && in_key_range(kx, ky, kz)) {
+                if (k2[c].x == key) e = bi;
+                else if (k2[c].y == key) e = bi + 1;
+                else if (k2[c].y != 0ull) slow |= 1u << c;   // both slots taken: the chain
+            }
+            p[c] = e;
+        }
+        while (slow) {
+            const int c = __builtin_ctz(slow);
+            slow &= slow - 1;
+            int kx = bx0, ky = by0, kz = bz0;
+            if (c & 1) kx = bx1;
+            if (c & 2) ky = by1;
+            if (c & 4) kz = bz1;
+            const unsigned long long key = pack_key(kx, ky, kz);
+            int32_t e = -1;
+            for (int32_t x = h.head[hash_index(kx, ky, kz, h.mask)]; x >= 0;) {
+                const Excess E = h.excess[x];
+                if (E.key == key) {
+                    e = 2 * h.n_buckets + x;
+                    break;
+                }
+                x = E.next;
+            }
+#pragma unroll
+            for (int r = 0; r < 8; r++)   // register selects, no indexed array
+                if (r == c) p[r] = e;
+        }
+        if (h.blk) {   // swapping: the entry's device voxel block, all 8 read together
+            int32_t q[8];
+#pragma unroll
+            for (int c = 0; c < 8; c++) q[c] = h.blk[max(p[c], 0)];
+#pragma unroll
+            for (int c = 0; c < 8; c++) p[c] = p[c] >= 0 ? q[c] : -1;
         }
         rmask = 0u;
         if (REF) {
+            int32_t st[8];
 #pragma unroll
-            for (int c = 0; c < 8; c++) rmask |= src.refined(p[c]) ? 1u << c : 0u;
+            for (int c = 0; c < 8; c++) st[c] = src.stamp[max(p[c], 0)];
+#pragma unroll
+            for (int c = 0; c < 8; c++) rmask |= (p[c] >= 0 && st[c] == src.frame) ? 1u << c : 0u;
         }
     }
 };
