@@ -41,8 +41,8 @@ VOX_BYTES = {"f32": 8, "f16": 4, "s16u8": 3}
 # another frame range, reports traffic null.
 FETCH_SCALE, WRITE_SCALE = 262144.0 / 131087.7, 262144.0 / 262144.0
 TRAFFIC_KIB = {
-    ("alloc", "f32", "vga", "10..299"): {"fetch": 1064.2, "write": 1022.0, "src": "eb5628d55d74cf82"},
-    ("integrate", "f32", "vga", "10..299"): {"fetch": 9985.2, "write": 14769.9, "src": "eb5628d55d74cf82"},
+    ("alloc", "f32", "vga", "10..299"): {"fetch": 1064.2, "write": 1022.0, "src": "b02bf5d61650a1b1"},
+    ("integrate", "f32", "vga", "10..299"): {"fetch": 9985.2, "write": 14769.9, "src": "b02bf5d61650a1b1"},
     ("raycast", "f32", "vga", "10..299"): {"fetch": 7422.9, "write": 9600.0, "src": "5bf9cb6448db0a80"},
 }
 

@@ -353,9 +353,10 @@ __device__ inline void alloc_pixel(const FuseArgs &a, int u, int v, float depth,
             for (int r = 0; r < 4; r++)
                 if (r == q) e4[r] = e;
         }
-        // The batch's stamp exchanges, all issued before any is waited for (the
-        // results are opaque to the compiler until all four are out, for the
-        // reason above): the first workgroup to stamp a block lists it.
+        // The batch's stamp exchanges, all issued before any is waited for: their
+        // results are hidden from the compiler until all four are out, as it
+        // would otherwise compare each result, and wait for it, before issuing
+        // the next.  The first workgroup to stamp a block lists it.
         uint32_t old4[4];
 #pragma unroll
         for (int q = 0; q < 4; q++) {
