@@ -128,6 +128,29 @@ def test_tracks_a_fused_scene_like_the_oracle():
     compare_systems(g, o)
 
 
+def test_repeated_calls_are_bit_identical():
+    """A step's partial sums cross the XCDs and are added by whichever workgroup
+    draws the last ticket, in a fixed order: repeated calls on the same inputs
+    return the same bits (a stale partial, or a ticket count not back at zero,
+    would not).  640 x 480, so that the finest level runs one workgroup per CU."""
+    itm, torch = gpu()
+    W, H, K = 640, 480, (525.0, 525.0, 319.5, 239.5)
+    T_true = moved(T_REF, [0.01, -0.02, 0.01], [0.02, -0.01, 0.015])
+    depth, V, N = corner_case(K, W, H, T_true)
+    d_g, V_g, N_g = upload(torch, depth, V, N)
+    sc = itm.Scene(0.01, 0.04, 100, 1 << 12, 1 << 10)
+    KK = K + (W, H)
+    print("case: corner 640x480, repeated systems and tracks", flush=True)
+    s0 = sc.icp_system(d_g, KK, 0, V_g, N_g, T_REF, T_true, 0.05)
+    T0, info0 = sc.track(d_g, KK, V_g, N_g, T_REF)
+    assert s0[28] > 50000 and info0["steps"] > 0
+    for _ in range(4):
+        np.testing.assert_array_equal(sc.icp_system(d_g, KK, 0, V_g, N_g, T_REF, T_true, 0.05), s0)
+        T, info = sc.track(d_g, KK, V_g, N_g, T_REF)
+        np.testing.assert_array_equal(T, T0)
+        assert info == info0
+
+
 def test_degenerate_inputs():
     itm, torch = gpu()
     W, H, K = 160, 120, (140.0, 140.0, 79.5, 59.5)
